@@ -1,0 +1,281 @@
+"""Seeded synthetic workloads for polarised A x W gridding.
+
+This module is shared by the FP64 oracle (tests) and the HIP path (bench).
+It only builds inputs: array layouts, Earth-rotation uvw tracks, source
+lists, the beam/leakage (Jones) model, w-plane placement and the per-plane
+support table.  None of the gridding, kernel-generation or imaging
+arithmetic lives here.
+
+The paper measured on ASKAP and ALMA measurement sets (Sec. 2.1, Sec. 2.3);
+none ships with it, so every workload here is synthetic, with the sizes of
+the five configurations the library is built for:
+
+  c1  Stokes-I, 256^2 grid, 8 w-planes, support 7, os 4, 20k visibilities
+  c2  full-pol A+W, 2048^2 x 4, 32 w-planes, support 16-48, os 8, 2.3M rows
+  c3  batched, 16 fields on their own 4096^2 x 4 grids, FP16 tables
+  c4  learned kernel surrogate (training draws)
+  c5  major cycle, 8192^2 x 4, 128 w-planes, 20M rows
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 2206151170
+C_LIGHT = 299792458.0
+DEG = math.pi / 180.0
+ARCSEC = DEG / 3600.0
+SIDEREAL_RATE = 2.0 * math.pi / 86164.0905  # rad/s
+
+
+@dataclass
+class Geometry:
+    """Grid, oversampling and w-plane layout shared by every stage.
+
+    n          grid side (even; image and uv grids are n x n)
+    cell       image pixel size in radians (the uv cell is 1/(n*cell) wavelengths)
+    os         oversampling factor of the kernel table (even)
+    w_planes   float64 [P], ascending w-plane centres in wavelengths
+    support    int32 [P], kernel support (taps per axis) of each plane
+    tile       int32 [P], uv tile side used to bin visibilities of each plane
+    aa_support support of the prolate-spheroidal anti-aliasing function
+    mk         samples per side of the image-domain lattice kernels are built on
+    """
+
+    n: int
+    cell: float
+    os: int
+    w_planes: np.ndarray
+    support: np.ndarray
+    tile: np.ndarray = None
+    aa_support: int = 7
+    mk: int = 0
+
+    def __post_init__(self):
+        self.w_planes = np.ascontiguousarray(self.w_planes, dtype=np.float64)
+        self.support = np.ascontiguousarray(self.support, dtype=np.int32)
+        if self.tile is None:
+            self.tile = default_tiles(self.support, 4)
+        self.tile = np.ascontiguousarray(self.tile, dtype=np.int32)
+        if self.mk == 0:
+            self.mk = self.n
+
+    @property
+    def fov(self) -> float:
+        return self.n * self.cell
+
+    @property
+    def nplanes(self) -> int:
+        return int(self.w_planes.shape[0])
+
+
+def default_tiles(support, q, lds_bytes=131072):
+    """Largest tile T (multiple of 4, >= 4) whose (T+S-1)^2 x q complex64 sub-grid fits lds_bytes."""
+    out = []
+    for s in np.asarray(support):
+        t = 4
+        while (t + 4 + int(s) - 1) ** 2 * q * 8 <= lds_bytes:
+            t += 4
+        out.append(t)
+    return np.asarray(out, dtype=np.int32)
+
+
+def linear_w_planes(nplanes: int, w_max: float) -> np.ndarray:
+    """Signed, symmetric, evenly spaced w-plane centres in [-w_max, w_max]."""
+    if nplanes == 1:
+        return np.zeros(1)
+    return np.array([-w_max + p * 2.0 * w_max / (nplanes - 1) for p in range(nplanes)])
+
+
+def support_rule(w_planes, fov, s_min=16, s_max=48):
+    """Per-plane support: 7 anti-aliasing taps plus the w-chirp spread, rounded up to even."""
+    s = [2 * math.ceil((7 + 0.8 * abs(w) * fov * fov) / 2.0) for w in w_planes]
+    return np.clip(np.asarray(s, dtype=np.int32), s_min, s_max).astype(np.int32)
+
+
+# --------------------------------------------------------------------------- arrays and tracks
+
+def antennas_in_disk(n_ant: int, radius_m: float, rng) -> np.ndarray:
+    """ENU positions (metres, flat, up = 0) uniform in a disk."""
+    r = radius_m * np.sqrt(rng.uniform(0.0, 1.0, n_ant))
+    t = rng.uniform(0.0, 2.0 * math.pi, n_ant)
+    return np.stack([r * np.cos(t), r * np.sin(t), np.zeros(n_ant)], axis=1)
+
+
+def baseline_pairs(n_ant: int) -> np.ndarray:
+    return np.array([(i, j) for i in range(n_ant) for j in range(i + 1, n_ant)], dtype=np.int32)
+
+
+def uvw_tracks(enu, lat, dec, hour_angles, freq_hz) -> np.ndarray:
+    """Textbook (H, dec) rotation of ENU baselines into uvw, in wavelengths.
+
+    Rows are time-major (all baselines of dump 0, then dump 1, ...), the order of
+    a measurement set.  Returns float64 [n_dumps * n_baselines, 3].
+    """
+    pairs = baseline_pairs(enu.shape[0])
+    b = enu[pairs[:, 1]] - enu[pairs[:, 0]]
+    e, nn, up = b[:, 0], b[:, 1], b[:, 2]
+    x = -math.sin(lat) * nn + math.cos(lat) * up
+    y = e
+    z = math.cos(lat) * nn + math.sin(lat) * up
+    h = np.asarray(hour_angles)[:, None]
+    sd, cd = math.sin(dec), math.cos(dec)
+    u = np.sin(h) * x + np.cos(h) * y
+    v = -sd * np.cos(h) * x + sd * np.sin(h) * y + cd * z
+    w = cd * np.cos(h) * x - cd * np.sin(h) * y + sd * z
+    lam = C_LIGHT / freq_hz
+    return np.stack([u, v, w], axis=-1).reshape(-1, 3) / lam
+
+
+# --------------------------------------------------------------------------- beam / leakage model
+
+@dataclass
+class GaussianLeakageBeam:
+    """Identical-antenna Jones model J = E(r) [[1, d_xy], [d_yx, 1]].
+
+    E is the voltage pattern exp(-2 ln2 (r/theta)^2), so the power beam E^2 has
+    FWHM theta.  d = level * (a + b l/theta + c m/theta) with seeded complex a, b, c.
+    """
+
+    theta: float
+    dxy: np.ndarray = field(default_factory=lambda: np.zeros(3, complex))
+    dyx: np.ndarray = field(default_factory=lambda: np.zeros(3, complex))
+    level: float = 0.01
+
+    def jones(self, l, m) -> np.ndarray:
+        l = np.asarray(l, dtype=np.float64)
+        m = np.asarray(m, dtype=np.float64)
+        r2 = l * l + m * m
+        e = np.exp(-2.0 * math.log(2.0) * r2 / (self.theta * self.theta))
+        dxy = self.level * (self.dxy[0] + self.dxy[1] * l / self.theta + self.dxy[2] * m / self.theta)
+        dyx = self.level * (self.dyx[0] + self.dyx[1] * l / self.theta + self.dyx[2] * m / self.theta)
+        j = np.empty(l.shape + (2, 2), dtype=np.complex128)
+        j[..., 0, 0] = e
+        j[..., 0, 1] = e * dxy
+        j[..., 1, 0] = e * dyx
+        j[..., 1, 1] = e
+        return j
+
+
+def seeded_leakage_beam(theta, rng, level=0.01) -> GaussianLeakageBeam:
+    def cn(k):
+        return (rng.standard_normal(k) + 1j * rng.standard_normal(k)) / math.sqrt(2.0)
+
+    return GaussianLeakageBeam(theta=theta, dxy=cn(3), dyx=cn(3), level=level)
+
+
+def lattice_coords(mk: int, fov: float) -> np.ndarray:
+    """Image-domain lattice the kernels are sampled on: (a - mk/2) * fov / mk."""
+    return (np.arange(mk) - mk // 2) * (fov / mk)
+
+
+def jones_on_lattice(beam, mk: int, fov: float) -> np.ndarray:
+    """complex128 [2][2][mk (m, rows)][mk (l, columns)], the layout make_kernels takes."""
+    x = lattice_coords(mk, fov)
+    mm, ll = np.meshgrid(x, x, indexing="ij")
+    j = beam.jones(ll, mm)  # [mk][mk][2][2]
+    return np.ascontiguousarray(np.moveaxis(j, (2, 3), (0, 1)))
+
+
+# --------------------------------------------------------------------------- sources and values
+
+def random_vis(nvis: int, npol: int, rng) -> np.ndarray:
+    """complex64 [nvis][npol], unit-variance complex normal."""
+    v = (rng.standard_normal((nvis, npol)) + 1j * rng.standard_normal((nvis, npol))) / math.sqrt(2)
+    return v.astype(np.complex64)
+
+
+@dataclass
+class Workload:
+    name: str
+    geom: Geometry
+    uvw: np.ndarray                  # float64 [nvis][3], wavelengths
+    npol: int                        # 1 (Stokes I) or 4 (XX, XY, YX, YY in, I, Q, U, V out)
+    src_l: np.ndarray = None
+    src_m: np.ndarray = None
+    src_iquv: np.ndarray = None      # [nsrc][npol]
+    beam: GaussianLeakageBeam = None
+    eps_null: float = 0.2
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def nvis(self):
+        return int(self.uvw.shape[0])
+
+
+def config1(seed: int = SEED_BASE + 1, nvis: int = 20000) -> Workload:
+    """Stokes-I, 256^2 grid, 8 planes |w| <= 200, PSWF support 7, os 4, no A-term."""
+    rng = np.random.default_rng(seed)
+    n = 256
+    cell = 0.1 / n
+    planes = linear_w_planes(8, 200.0)
+    geom = Geometry(n=n, cell=cell, os=4, w_planes=planes, support=np.full(8, 7, np.int32),
+                    tile=np.full(8, 16, np.int32), aa_support=7, mk=n)
+    r = 100.0 * np.sqrt(rng.uniform(0, 1, nvis))
+    t = rng.uniform(0, 2 * math.pi, nvis)
+    w = rng.uniform(-200.0, 200.0, nvis)
+    uvw = np.stack([r * np.cos(t), r * np.sin(t), w], axis=1)
+    half = 0.25 * geom.fov
+    sl = rng.uniform(-half, half, 5)
+    sm = rng.uniform(-half, half, 5)
+    flux = rng.uniform(0.1, 1.0, 5)
+    return Workload("c1-stokesI-256", geom, uvw, 1, sl, sm, flux[:, None])
+
+
+ASKAP_LAT = -26.7 * DEG
+
+
+def polarised_sources(nsrc, r_max, rng):
+    r = r_max * np.sqrt(rng.uniform(0, 1, nsrc))
+    t = rng.uniform(0, 2 * math.pi, nsrc)
+    i = rng.uniform(0.1, 1.0, nsrc)
+    p = rng.uniform(0.0, 0.1, nsrc)
+    chi = rng.uniform(0.0, math.pi, nsrc)
+    vfrac = rng.uniform(-0.01, 0.01, nsrc)
+    iquv = np.stack([i, p * i * np.cos(2 * chi), p * i * np.sin(2 * chi), vfrac * i], axis=1)
+    return r * np.cos(t), r * np.sin(t), iquv
+
+
+def config2(seed: int = SEED_BASE + 2, nvis: int = 2_300_000, n: int = 2048,
+            nplanes: int = 32, cell: float = 7.0 * ARCSEC, freq: float = 1.4e9,
+            mk: int = 256) -> Workload:
+    """Full-pol A+W: 36 antennas (630 baselines), 8 h tracks, 50 polarised sources."""
+    rng = np.random.default_rng(seed)
+    enu = antennas_in_disk(36, 1500.0, rng)
+    nbl = 36 * 35 // 2
+    ndump = -(-nvis // nbl)
+    ha = np.linspace(-4.0, 4.0, ndump) * (15.0 * DEG)
+    uvw = uvw_tracks(enu, ASKAP_LAT, -45.0 * DEG, ha, freq)[:nvis]
+    fov = n * cell
+    w_max = math.ceil(np.abs(uvw[:, 2]).max() / 100.0) * 100.0
+    planes = linear_w_planes(nplanes, w_max)
+    support = support_rule(planes, fov)
+    geom = Geometry(n=n, cell=cell, os=8, w_planes=planes, support=support,
+                    tile=default_tiles(support, 4), aa_support=7, mk=mk)
+    beam = seeded_leakage_beam(1.0 * DEG, rng)
+    sl, sm, iquv = polarised_sources(50, 1.0 * DEG, rng)
+    return Workload("c2-fullpol-AW-2048", geom, uvw, 4, sl, sm, iquv, beam, 0.2,
+                    extra={"freq_hz": freq, "n_ant": 36, "n_dumps": ndump})
+
+
+def scaled_config2(nvis: int, n: int = 256, nplanes: int = 8, seed: int = SEED_BASE + 2,
+                   mk: int = 64, support=None, tile=None) -> Workload:
+    """Config-2 physics on a smaller grid for oracle-sized parity cases.
+
+    Same array, tracks, beam and leakage; the 7 arcsec cell is kept so the uv tracks still
+    fill the grid (the field of view shrinks with n).  `support` overrides the per-plane
+    support table (default: the support rule with a floor of 8 taps).
+    """
+    w = config2(seed=seed, nvis=nvis, n=n, nplanes=nplanes, mk=mk)
+    g = w.geom
+    if support is None:
+        support = support_rule(g.w_planes, g.fov, s_min=8, s_max=48)
+    support = np.asarray(support, dtype=np.int32)
+    if tile is None:
+        tile = default_tiles(support, 4)
+    w.geom = Geometry(n=g.n, cell=g.cell, os=g.os, w_planes=g.w_planes, support=support,
+                      tile=np.asarray(tile, dtype=np.int32), aa_support=g.aa_support, mk=mk)
+    w.name = f"c2-fullpol-AW-{n}"
+    return w
