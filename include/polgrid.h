@@ -1,0 +1,188 @@
+/*
+ * polgrid: full-polarisation A x W-projection convolutional gridding and
+ * degridding for AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv 2206.15117, "A GPU-based Imager with Polarised Primary-beam
+ * Correction".  Visibilities are spread onto (or read back from) the uv grid
+ * through oversampled kernels, each the Fourier transform of an anti-aliasing
+ * function times a w-correction screen times one cell of a 4x4 Mueller matrix
+ * (Sec. 3.2); gridding kernels come from the null-regularised inverse of the
+ * Stokes Mueller matrix (Sec. 3.3, Eq. 6).
+ *
+ * Conventions used by every call
+ *   - Grid side n (even).  Image pixel (i, j) is at l = (j - n/2) cell,
+ *     m = (i - n/2) cell; visibility (u, v) sits at grid position
+ *     x = u n cell + n/2, y = v n cell + n/2, snapped in float64 onto the
+ *     1/os fine grid with round-half-up.
+ *   - Kernel footprint: the S x S box of grid points starting at
+ *     X0 = ceil((fine - S os/2 + 1) / os); visibilities whose box leaves
+ *     [0, n) are dropped (not gridded; degridded to 0).
+ *   - W-plane: nearest plane centre, ties to the lower plane.
+ *   - npol = 1: Stokes I only (one correlation in, one grid out).
+ *     npol = 4: correlations XX, XY, YX, YY in; Stokes I, Q, U, V grids out
+ *     (Eq. 3, Eq. 4 with U = (XY + YX)/2).
+ *   - Visibilities: complex64 [nvis][npol] (interleaved re, im), device memory.
+ *   - Grids: complex64 planar [npol][n][n] (row = v, column = u), device memory.
+ *   - Images: float32 [npol][n][n], device memory.
+ *   - uvw: float64 [nvis][3] in wavelengths, device memory.
+ *   - Weights are not part of the interface: callers pre-multiply visibilities,
+ *     which keeps pg_grid and pg_degrid an exact adjoint pair.
+ *
+ * Ownership: the caller owns every buffer passed in; the library owns
+ * pg_kernels and pg_plan objects, which are immutable after creation and may
+ * be shared between streams and threads.  Their device memory comes from the
+ * allocator registered with pg_set_allocator (hipMalloc/hipFree by default).
+ *
+ * Errors: every int-returning call returns PG_OK (0) or a negative PG_E* code;
+ * arguments are validated on the host before anything is enqueued, and the
+ * reason is available from pg_last_error().  No C++ exception crosses the ABI.
+ *
+ * Asynchrony: pg_grid, pg_degrid and pg_taper only enqueue work on `stream`
+ * (a hipStream_t, NULL for the default stream).  pg_make_kernels and
+ * pg_plan_create synchronise `stream` once before returning.
+ */
+#ifndef POLGRID_H
+#define POLGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PG_OK 0
+#define PG_EINVAL (-1)       /* bad argument; nothing was enqueued */
+#define PG_ENOMEM (-2)       /* the allocator returned NULL */
+#define PG_EHIP (-3)         /* a HIP runtime call failed */
+#define PG_EUNSUPPORTED (-4) /* valid request this build does not handle */
+
+#define PG_KIND_GRID 0   /* screens (M'^S)^-1 S: correlations -> Stokes (Sec. 3.2-3.3) */
+#define PG_KIND_DEGRID 1 /* screens (S^-1 M^S)^H: conjugate maps Stokes sky -> correlations (Eq. 2) */
+
+#define PG_STORE_F32 0 /* table entries complex64 */
+#define PG_STORE_F16 1 /* table entries two float16 (re, im); arithmetic stays float32 */
+
+#define PG_STOKES_IAU 0   /* U = (XY + YX)/2 */
+#define PG_STOKES_PAPER 1 /* U = i (XY + YX)/2 as printed in Eq. 4 */
+
+/* pg_grid / pg_degrid flags */
+#define PG_ACCUMULATE 1 /* pg_grid: add onto the existing grid instead of overwriting it */
+#define PG_FFTSHIFT 2   /* the grid in memory is G(X,Y) (-1)^(X+Y): the centring modulation
+                           the FFT needs is folded into the grid flush / degrid gather */
+
+/* pg_taper directions */
+#define PG_TAPER_IMAGE 0   /* complex FFT output -> real image / (AA(l) AA(m)) / weight_sum */
+#define PG_TAPER_PREDICT 1 /* real model image -> complex (model / (AA(l) AA(m))) for the inverse FFT */
+
+typedef struct pg_geometry {
+  int32_t n;               /* grid side, even, 8 .. 16384 */
+  double cell;             /* image pixel size, radians */
+  int32_t os;              /* oversampling factor, even, 2 .. 16 */
+  int32_t nplanes;         /* number of w-planes, 1 .. 1024 */
+  const double* w_planes;  /* host [nplanes], ascending, wavelengths */
+  const int32_t* support;  /* host [nplanes], taps per axis, 1 .. 64 */
+  const int32_t* tile;     /* host [nplanes], uv tile side used to bin visibilities, >= 1 */
+  int32_t aa_support;      /* support of the prolate spheroidal anti-aliasing function (7) */
+  int32_t mk;              /* samples per side of the image lattice kernels are built on (even) */
+} pg_geometry;
+
+typedef struct pg_kernel_spec {
+  pg_geometry g;
+  int32_t npol;              /* 1 or 4 */
+  int32_t kind;              /* PG_KIND_GRID or PG_KIND_DEGRID */
+  const double* jones;       /* host complex128 [2][2][mk][mk] (row = m, column = l) on the lattice
+                                l_a = (a - mk/2) n cell / mk; NULL = no A-term (identity) */
+  double eps_null;           /* Eq. 6 mask fraction epsilon (0.2 typical); used by PG_KIND_GRID */
+  int32_t stokes_convention; /* PG_STOKES_IAU or PG_STOKES_PAPER */
+  int32_t storage;           /* PG_STORE_F32 or PG_STORE_F16 */
+} pg_kernel_spec;
+
+typedef struct pg_kernels pg_kernels;
+typedef struct pg_plan pg_plan;
+
+/* Read-only view of a kernel set, for inspection and tests. */
+typedef struct pg_kernels_desc {
+  int32_t npol, kind, storage, os, n, nplanes;
+  const void* table;            /* device; per plane [os][os][S][S][npol][npol] entries
+                                   (phase_y, phase_x, tap_y, tap_x, q, c); tap t of phase ph
+                                   has fine-grid offset ph - S os/2 + 1 + t os */
+  const int64_t* plane_offset;  /* host [nplanes + 1], offsets into table in entries */
+  const double* aa_pixels;      /* host [n], anti-aliasing function at the image pixels */
+} pg_kernels_desc;
+
+/* Read-only view of a plan, for inspection and tests. */
+typedef struct pg_plan_desc {
+  int64_t nvis, n_kept, n_dropped, n_items;
+  const int32_t* perm;   /* device [nvis]: visibility index in binned order, kept first */
+  const int32_t* fine;   /* device [n_kept][2]: (fine_x, fine_y) in binned order */
+  const int32_t* items;  /* device [n_items][8]: plane, origin_y, origin_x, start, end, 0, 0, 0 */
+} pg_plan_desc;
+
+/* Library version, (major << 16) | minor. */
+int pg_version(void);
+
+/* Message for the last failing call on this thread; valid until the next pg_* call. */
+const char* pg_last_error(void);
+
+/* Device memory hooks.  alloc(bytes, stream, ctx) returns device memory or NULL;
+ * free(ptr, stream, ctx) releases it.  Passing NULL restores hipMalloc/hipFree.
+ * Applies to objects created afterwards. */
+void pg_set_allocator(void* (*alloc_fn)(size_t, void*, void*),
+                      void (*free_fn)(void*, void*, void*), void* ctx);
+
+/* Kernel generation (Sec. 3.2: image-domain anti-aliasing x w-correction x Mueller
+ * cell, Fourier transformed into the uv domain; Sec. 3.3, Eq. 6 for gridding).
+ * For plane p, output q and input c the table holds the zero-padded (x os)
+ * inverse DFT of f = AA(l) AA(m) exp(-2 pi i w_p (n-1)) Phi_qc(l, m) sampled on
+ * the mk x mk lattice, restricted to offsets |d| < S_p os / 2.  Host float64
+ * Mueller algebra, device float64 transforms, stored in spec->storage.
+ * Synchronises `stream`.  Errors: PG_EINVAL (bad spec), PG_EUNSUPPORTED (sub-grid
+ * of some plane larger than the LDS budget), PG_ENOMEM, PG_EHIP. */
+int pg_make_kernels(const pg_kernel_spec* spec, void* stream, pg_kernels** out);
+int pg_kernels_info(const pg_kernels* k, pg_kernels_desc* out);
+/* Copy the whole table (plane_offset[nplanes] entries of 8 bytes (F32) or 4 bytes (F16)) into
+ * caller device memory `dst`; enqueue only. */
+int pg_kernels_copy_table(const pg_kernels* k, void* dst, void* stream);
+void pg_kernels_destroy(pg_kernels* k);
+
+/* Visibility binning: float64 uvw -> fine positions, w-plane, anchor tile and
+ * oversampling phase; stable sort by (plane, tile_y, tile_x, phase_y, phase_x);
+ * work items are runs of one (plane, tile) cut into chunks of at most max_chunk.
+ * Synchronises `stream` once and returns the drop count in *n_dropped (host, may be NULL).
+ * nvis may be 0.  Errors: PG_EINVAL, PG_ENOMEM, PG_EHIP. */
+int pg_plan_create(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_chunk,
+                   void* stream, pg_plan** out, int64_t* n_dropped);
+int pg_plan_info(const pg_plan* p, pg_plan_desc* out);
+/* Copy the plan's perm [nvis], fine [n_kept][2] and items [n_items][8] int32 arrays into caller
+ * device memory (any destination may be NULL); enqueue only. */
+int pg_plan_copy(const pg_plan* p, int32_t* perm, int32_t* fine, int32_t* items, void* stream);
+void pg_plan_destroy(pg_plan* p);
+
+/* Gridding (Sec. 3.2, Sec. 4):
+ *   G_q(X,Y) (+)= sum_k sum_c T_{p_k,q,c}(X os - fine_x,k, Y os - fine_y,k) V_{k,c}.
+ * vis: complex64 [nvis][npol] (the plan's nvis); grid: complex64 [npol][n][n].
+ * Without PG_ACCUMULATE the grid is overwritten.  Enqueue only. */
+int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, int32_t flags,
+            void* stream);
+
+/* Degridding, the exact adjoint of pg_grid (Sec. 3.2, degridding stage):
+ *   V_{k,c} = sum_q sum_{X,Y} conj(T_{p_k,q,c}(...)) G_q(X, Y); dropped visibilities get 0.
+ * grid: complex64 [npol][n][n]; vis_out: complex64 [nvis][npol].  Enqueue only. */
+int pg_degrid(const pg_plan* p, const pg_kernels* k, const void* grid, void* vis_out, int32_t flags,
+              void* stream);
+
+/* Image-domain taper correction around the FFT (Sec. 2.2, Sec. 3.2).
+ * PG_TAPER_IMAGE:   in complex64 [npol][n][n] = FFT of a PG_FFTSHIFT grid;
+ *                   out float32 [npol][n][n] = Re((-1)^(i+j) in) / (AA(l_j) AA(m_i)) / weight_sum.
+ * PG_TAPER_PREDICT: in float32 [npol][n][n] model; out complex64 [npol][n][n] =
+ *                   (-1)^(i+j) model / (AA AA), ready for an unnormalised inverse FFT
+ *                   whose result is a PG_FFTSHIFT grid.
+ * Enqueue only.  Errors: PG_EINVAL. */
+int pg_taper(const pg_kernels* k, const void* in, void* out, int32_t direction, double weight_sum,
+             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POLGRID_H */

@@ -53,10 +53,13 @@ def dft_table(f2d: np.ndarray, support: int, os: int) -> np.ndarray:
     return pad.reshape(support, os, support, os).transpose(1, 3, 0, 2)
 
 
-def make_tables(geom, phi: np.ndarray) -> list:
-    """One table per plane, each [Q][C][os][os][S_p][S_p] complex128."""
+def make_tables(geom, phi: np.ndarray, planes=None) -> list:
+    """One table per plane, each [Q][C][os][os][S_p][S_p] complex128 (None for planes not asked for)."""
     tables = []
     for p in range(geom.nplanes):
+        if planes is not None and p not in planes:
+            tables.append(None)
+            continue
         f = image_function(geom, p, phi)
         q, c = f.shape[:2]
         s = int(geom.support[p])
@@ -72,7 +75,9 @@ def round_tables(tables, dtype) -> list:
     """Tables rounded to the storage precision (complex64, or float16 pairs) and back to complex128."""
     out = []
     for t in tables:
-        if dtype == np.float16:
+        if t is None:
+            out.append(None)
+        elif dtype == np.float16:
             out.append(t.real.astype(np.float16).astype(np.float64)
                        + 1j * t.imag.astype(np.float16).astype(np.float64))
         else:

@@ -1,0 +1,367 @@
+// C-ABI entry points: host-side validation, kernel generation orchestration,
+// plan construction and launch dispatch.  No C++ exception crosses the ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace pg {
+
+namespace {
+thread_local std::string g_error;
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+constexpr size_t kLdsBudget = 160 * 1024;
+
+int fail(int code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PG_HIP(call, what)                   \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+int check_geometry(const pg_geometry& g, int npol) {
+  if (g.n < 8 || g.n > 16384 || (g.n & 1)) return fail(PG_EINVAL, "n must be even and in [8, 16384]");
+  if (!(g.cell > 0.0) || !is_finite(g.cell)) return fail(PG_EINVAL, "cell must be positive and finite");
+  if (g.n * g.cell >= 2.0) return fail(PG_EINVAL, "field of view n*cell must be below 2 (direction cosines)");
+  if (g.os < 2 || g.os > 16 || (g.os & 1)) return fail(PG_EINVAL, "os must be even and in [2, 16]");
+  if (g.nplanes < 1 || g.nplanes > 1024) return fail(PG_EINVAL, "nplanes must be in [1, 1024]");
+  if (!g.w_planes || !g.support || !g.tile) return fail(PG_EINVAL, "w_planes, support and tile must be non-NULL");
+  for (int p = 0; p < g.nplanes; ++p) {
+    if (!is_finite(g.w_planes[p])) return fail(PG_EINVAL, "w_planes must be finite");
+    if (p && !(g.w_planes[p] > g.w_planes[p - 1])) return fail(PG_EINVAL, "w_planes must be strictly ascending");
+    if (g.support[p] < 1 || g.support[p] > 64) return fail(PG_EINVAL, "support must be in [1, 64]");
+    if (g.support[p] > g.n) return fail(PG_EINVAL, "support must not exceed n");
+    if (g.tile[p] < 1 || g.tile[p] > g.n) return fail(PG_EINVAL, "tile must be in [1, n]");
+    const size_t w = static_cast<size_t>(g.tile[p]) + g.support[p] - 1;
+    if (w * w * npol * 8 > kLdsBudget)
+      return fail(PG_EUNSUPPORTED, "plane " + std::to_string(p) + ": sub-grid (tile + support - 1)^2 x npol x 8 B exceeds 160 KiB of LDS");
+  }
+  if (g.aa_support < 1 || g.aa_support > 64) return fail(PG_EINVAL, "aa_support must be in [1, 64]");
+  if (g.mk < 2 || g.mk > 4096 || (g.mk & 1)) return fail(PG_EINVAL, "mk must be even and in [2, 4096]");
+  return PG_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+
+namespace {
+
+int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** out) {
+  if (!spec || !out) return fail(PG_EINVAL, "spec and out must be non-NULL");
+  *out = nullptr;
+  if (spec->npol != 1 && spec->npol != 4) return fail(PG_EINVAL, "npol must be 1 or 4");
+  if (spec->kind != PG_KIND_GRID && spec->kind != PG_KIND_DEGRID) return fail(PG_EINVAL, "kind must be PG_KIND_GRID or PG_KIND_DEGRID");
+  if (spec->storage != PG_STORE_F32 && spec->storage != PG_STORE_F16) return fail(PG_EINVAL, "storage must be PG_STORE_F32 or PG_STORE_F16");
+  if (spec->stokes_convention != PG_STOKES_IAU && spec->stokes_convention != PG_STOKES_PAPER)
+    return fail(PG_EINVAL, "stokes_convention must be PG_STOKES_IAU or PG_STOKES_PAPER");
+  if (!(spec->eps_null >= 0.0) || !is_finite(spec->eps_null)) return fail(PG_EINVAL, "eps_null must be finite and >= 0");
+  int rc = check_geometry(spec->g, spec->npol);
+  if (rc != PG_OK) return rc;
+  if (spec->npol == 1 && spec->jones) return fail(PG_EUNSUPPORTED, "npol = 1 (Stokes I only) takes no Jones field");
+
+  const pg_geometry& g = spec->g;
+  const int mk = g.mk, np = spec->npol, nqc = np * np;
+  std::vector<double> phi;
+  std::string err;
+  if (!build_screens(np, spec->kind, spec->jones, mk, spec->eps_null, spec->stokes_convention, phi, err))
+    return fail(PG_EINVAL, err);
+
+  auto* k = new (std::nothrow) pg_kernels();
+  if (!k) return fail(PG_ENOMEM, "host allocation failed");
+  std::unique_ptr<pg_kernels> guard(k);
+  k->npol = np;
+  k->kind = spec->kind;
+  k->storage = spec->storage;
+  k->os = g.os;
+  k->n = g.n;
+  k->nplanes = g.nplanes;
+  k->mk = mk;
+  k->aa_support = g.aa_support;
+  k->cell = g.cell;
+  k->w_planes.assign(g.w_planes, g.w_planes + g.nplanes);
+  k->support.assign(g.support, g.support + g.nplanes);
+  k->tile.assign(g.tile, g.tile + g.nplanes);
+  k->plane_offset.assign(g.nplanes + 1, 0);
+  std::vector<PlaneInfo> pinfo(g.nplanes);
+  int smax = 0;
+  for (int p = 0; p < g.nplanes; ++p) {
+    const int64_t S = g.support[p];
+    k->plane_offset[p + 1] = k->plane_offset[p] + static_cast<int64_t>(g.os) * g.os * S * S * nqc;
+    pinfo[p].offset = k->plane_offset[p];
+    pinfo[p].support = g.support[p];
+    pinfo[p].tile = g.tile[p];
+    pinfo[p].width = g.tile[p] + g.support[p] - 1;
+    pinfo[p].pad = 0;
+    k->max_width = std::max(k->max_width, pinfo[p].width);
+    smax = std::max(smax, g.support[p]);
+  }
+  k->lds_bytes = static_cast<size_t>(k->max_width) * k->max_width * np * 8;
+
+  // Anti-aliasing function on the kernel lattice and at the image pixels.
+  const double c = M_PI * g.aa_support / 2.0;
+  std::vector<double> xl(mk), xp(g.n);
+  for (int a = 0; a < mk; ++a) xl[a] = 2.0 * (a - mk / 2) / mk;
+  for (int j = 0; j < g.n; ++j) xp[j] = 2.0 * (j - g.n / 2) / g.n;
+  std::vector<double> aa_lat = pswf0(c, xl);
+  k->aa_pixels = pswf0(c, xp);
+  std::vector<double> inv_aa(g.n);
+  for (int j = 0; j < g.n; ++j) inv_aa[j] = 1.0 / k->aa_pixels[j];
+
+  const size_t entry = spec->storage == PG_STORE_F16 ? 4 : 8;
+  const size_t npix = static_cast<size_t>(mk) * mk;
+  const size_t lmax = static_cast<size_t>(smax) * g.os;
+  DevBuf phi_d, aa_d, f_d, e_d, a_d, t_d;
+  if (!k->table.alloc(k->plane_offset.back() * entry, s) || !k->planes.alloc(sizeof(PlaneInfo) * g.nplanes, s) ||
+      !k->w_dev.alloc(sizeof(double) * g.nplanes, s) || !k->inv_aa.alloc(sizeof(double) * g.n, s) ||
+      !phi_d.alloc(sizeof(double2) * nqc * npix, s) || !aa_d.alloc(sizeof(double) * mk, s) ||
+      !f_d.alloc(sizeof(double2) * nqc * npix, s) || !e_d.alloc(sizeof(double2) * lmax * mk, s) ||
+      !a_d.alloc(sizeof(double2) * nqc * mk * lmax, s) || !t_d.alloc(sizeof(double2) * nqc * lmax * lmax, s))
+    return fail(PG_ENOMEM, "device allocation failed in make_kernels");
+
+  PG_HIP(hipMemcpyAsync(phi_d.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice, s), "upload screens");
+  PG_HIP(hipMemcpyAsync(aa_d.p, aa_lat.data(), mk * sizeof(double), hipMemcpyHostToDevice, s), "upload AA");
+  PG_HIP(hipMemcpyAsync(k->planes.p, pinfo.data(), pinfo.size() * sizeof(PlaneInfo), hipMemcpyHostToDevice, s), "upload planes");
+  PG_HIP(hipMemcpyAsync(k->w_dev.p, k->w_planes.data(), g.nplanes * sizeof(double), hipMemcpyHostToDevice, s), "upload w");
+  PG_HIP(hipMemcpyAsync(k->inv_aa.p, inv_aa.data(), g.n * sizeof(double), hipMemcpyHostToDevice, s), "upload taper");
+  const double fov = g.n * g.cell;
+  for (int p = 0; p < g.nplanes; ++p) {
+    const int S = g.support[p];
+    const int len = S * g.os;
+    PG_HIP(launch_screen(phi_d.as<double2>(), aa_d.as<double>(), g.w_planes[p], fov, mk, nqc, f_d.as<double2>(), s), "screen");
+    PG_HIP(launch_twiddles(S, g.os, mk, e_d.as<double2>(), s), "twiddles");
+    // A[qc][b][dx] = sum_a F[qc][b][a] E[dx][a]
+    PG_HIP(launch_zgemm_nt(nqc, mk, len, mk, f_d.as<double2>(), npix, e_d.as<double2>(), 0, a_d.as<double2>(),
+                           static_cast<int64_t>(mk) * len, s), "dft stage 1");
+    // T[qc][dy][dx] = sum_b E[dy][b] A[qc][b][dx]
+    PG_HIP(launch_zgemm_nn(nqc, len, len, mk, e_d.as<double2>(), 0, a_d.as<double2>(), static_cast<int64_t>(mk) * len,
+                           t_d.as<double2>(), static_cast<int64_t>(len) * len, s), "dft stage 2");
+    void* dst = static_cast<char*>(k->table.p) + k->plane_offset[p] * entry;
+    PG_HIP(launch_pack(t_d.as<double2>(), S, g.os, nqc, spec->storage, dst, s), "pack");
+  }
+  PG_HIP(hipStreamSynchronize(s), "make_kernels sync");
+  *out = guard.release();
+  return PG_OK;
+}
+
+bool same_geometry(const pg_plan* p, const pg_kernels* k) {
+  return p->n == k->n && p->os == k->os && p->support == k->support && p->tile == k->tile;
+}
+
+int plan_impl(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_chunk, hipStream_t s, pg_plan** out,
+              int64_t* n_dropped) {
+  if (!k || !out) return fail(PG_EINVAL, "kernels and out must be non-NULL");
+  *out = nullptr;
+  if (nvis < 0 || nvis > 0x7ffffff0LL) return fail(PG_EINVAL, "nvis must be in [0, 2^31 - 16]");
+  if (nvis > 0 && !uvw) return fail(PG_EINVAL, "uvw must be non-NULL when nvis > 0");
+  if (max_chunk < 1) return fail(PG_EINVAL, "max_chunk must be >= 1");
+  auto* p = new (std::nothrow) pg_plan();
+  if (!p) return fail(PG_ENOMEM, "host allocation failed");
+  std::unique_ptr<pg_plan> guard(p);
+  p->nvis = nvis;
+  p->max_chunk = max_chunk;
+  p->n = k->n;
+  p->os = k->os;
+  p->support = k->support;
+  p->tile = k->tile;
+  const int min_tile = *std::min_element(k->tile.begin(), k->tile.end());
+  const int nt = (k->n + min_tile - 1) / min_tile;
+  const unsigned __int128 nbins = static_cast<unsigned __int128>(k->nplanes) * nt * nt * k->os * k->os;
+  int bits = 1;
+  while (bits < 64 && (static_cast<unsigned __int128>(1) << bits) <= nbins) ++bits;  // 2^bits > max key + 1
+  if ((static_cast<unsigned __int128>(1) << bits) <= nbins) return fail(PG_EUNSUPPORTED, "binning key exceeds 64 bits");
+  const uint64_t drop_key = bits == 64 ? ~0ull : ((1ull << bits) - 1);
+  if (!p->counter.alloc(sizeof(int32_t) * 4, s)) return fail(PG_ENOMEM, "device allocation failed in plan");
+  if (nvis == 0) {
+    if (n_dropped) *n_dropped = 0;
+    *out = guard.release();
+    return PG_OK;
+  }
+  DevBuf keys, keys_t, vals, vals_t, fine_all, scratch, counts;
+  const int64_t sc = std::max(radix_scratch_elems(nvis), plan_scratch_elems(nvis));
+  if (!keys.alloc(8 * nvis, s) || !keys_t.alloc(8 * nvis, s) || !vals.alloc(4 * nvis, s) ||
+      !vals_t.alloc(4 * nvis, s) || !fine_all.alloc(8 * nvis, s) || !scratch.alloc(4 * sc, s) ||
+      !counts.alloc(16, s) || !p->perm.alloc(4 * nvis, s))
+    return fail(PG_ENOMEM, "device allocation failed in plan");
+  PG_HIP(launch_fill_zero(counts.p, 16, s), "zero counts");
+  PG_HIP(launch_plan_keys(uvw, nvis, k->n, k->cell, k->os, k->nplanes, k->w_dev.as<double>(), k->planes.as<PlaneInfo>(),
+                          nt, drop_key, keys.as<uint64_t>(), vals.as<int32_t>(), fine_all.as<int2>(), s), "plan keys");
+  bool in_tmp = false;
+  PG_HIP(radix_sort_pairs(keys.as<uint64_t>(), vals.as<int32_t>(), keys_t.as<uint64_t>(), vals_t.as<int32_t>(), nvis,
+                          bits, scratch.as<int32_t>(), sc, s, &in_tmp), "radix sort");
+  const uint64_t* ks = in_tmp ? keys_t.as<uint64_t>() : keys.as<uint64_t>();
+  const int32_t* vs = in_tmp ? vals_t.as<int32_t>() : vals.as<int32_t>();
+  PG_HIP(launch_plan_stage_a(ks, nvis, drop_key, k->os, max_chunk, counts.as<int32_t>(), scratch.as<int32_t>(), sc, s),
+         "plan items");
+  int32_t hc[4] = {0, 0, 0, 0};
+  PG_HIP(hipMemcpyAsync(hc, counts.p, 16, hipMemcpyDeviceToHost, s), "read counts");
+  PG_HIP(hipStreamSynchronize(s), "plan sync");
+  p->n_kept = hc[0];
+  p->n_items = hc[1];
+  const int64_t n_runs = hc[2];
+  p->n_dropped = nvis - p->n_kept;
+  if (!p->fine.alloc(8 * std::max<int64_t>(p->n_kept, 1), s) || !p->items.alloc(sizeof(Item) * std::max<int64_t>(p->n_items, 1), s))
+    return fail(PG_ENOMEM, "device allocation failed in plan");
+  PG_HIP(hipMemcpyAsync(p->perm.p, vs, 4 * nvis, hipMemcpyDeviceToDevice, s), "copy perm");
+  PG_HIP(launch_plan_scatter(ks, vs, fine_all.as<int2>(), p->n_kept, n_runs, nvis, k->os, nt, max_chunk,
+                             k->planes.as<PlaneInfo>(), scratch.as<int32_t>(), p->fine.as<int2>(), p->items.as<Item>(), s),
+         "plan scatter");
+  PG_HIP(hipStreamSynchronize(s), "plan sync");
+  if (n_dropped) *n_dropped = p->n_dropped;
+  *out = guard.release();
+  return PG_OK;
+}
+
+int check_run(const pg_plan* p, const pg_kernels* k, const void* a, const void* b, int32_t flags, int allowed) {
+  if (!p || !k) return fail(PG_EINVAL, "plan and kernels must be non-NULL");
+  if (!b) return fail(PG_EINVAL, "output buffer must be non-NULL");
+  if (!a && p->nvis > 0) return fail(PG_EINVAL, "input buffer must be non-NULL");
+  if (flags & ~allowed) return fail(PG_EINVAL, "unknown flag bits");
+  if (!same_geometry(p, k)) return fail(PG_EINVAL, "plan was built for a different geometry than these kernels");
+  return PG_OK;
+}
+
+}  // namespace
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+int pg_version(void) { return (1 << 16) | 0; }
+
+const char* pg_last_error(void) { return g_error.c_str(); }
+
+void pg_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(void*, void*, void*), void* ctx) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (!alloc_fn || !free_fn) {
+    g_alloc = Allocator();
+  } else {
+    g_alloc.alloc_fn = alloc_fn;
+    g_alloc.free_fn = free_fn;
+    g_alloc.ctx = ctx;
+  }
+}
+
+int pg_make_kernels(const pg_kernel_spec* spec, void* stream, pg_kernels** out) {
+  g_error.clear();
+  try {
+    return make_kernels_impl(spec, static_cast<hipStream_t>(stream), out);
+  } catch (...) {
+    return fail(PG_ENOMEM, "exception in make_kernels");
+  }
+}
+
+int pg_kernels_info(const pg_kernels* k, pg_kernels_desc* out) {
+  g_error.clear();
+  if (!k || !out) return fail(PG_EINVAL, "kernels and out must be non-NULL");
+  out->npol = k->npol;
+  out->kind = k->kind;
+  out->storage = k->storage;
+  out->os = k->os;
+  out->n = k->n;
+  out->nplanes = k->nplanes;
+  out->table = k->table.p;
+  out->plane_offset = k->plane_offset.data();
+  out->aa_pixels = k->aa_pixels.data();
+  return PG_OK;
+}
+
+int pg_kernels_copy_table(const pg_kernels* k, void* dst, void* stream) {
+  g_error.clear();
+  if (!k || !dst) return fail(PG_EINVAL, "kernels and dst must be non-NULL");
+  PG_HIP(hipMemcpyAsync(dst, k->table.p, k->table.bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+         "copy table");
+  return PG_OK;
+}
+
+void pg_kernels_destroy(pg_kernels* k) { delete k; }
+
+int pg_plan_create(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_chunk, void* stream,
+                   pg_plan** out, int64_t* n_dropped) {
+  g_error.clear();
+  try {
+    return plan_impl(k, uvw, nvis, max_chunk, static_cast<hipStream_t>(stream), out, n_dropped);
+  } catch (...) {
+    return fail(PG_ENOMEM, "exception in plan_create");
+  }
+}
+
+int pg_plan_info(const pg_plan* p, pg_plan_desc* out) {
+  g_error.clear();
+  if (!p || !out) return fail(PG_EINVAL, "plan and out must be non-NULL");
+  out->nvis = p->nvis;
+  out->n_kept = p->n_kept;
+  out->n_dropped = p->n_dropped;
+  out->n_items = p->n_items;
+  out->perm = p->perm.as<int32_t>();
+  out->fine = p->fine.as<int32_t>();
+  out->items = p->items.as<int32_t>();
+  return PG_OK;
+}
+
+int pg_plan_copy(const pg_plan* p, int32_t* perm, int32_t* fine, int32_t* items, void* stream) {
+  g_error.clear();
+  if (!p) return fail(PG_EINVAL, "plan must be non-NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (perm && p->nvis) PG_HIP(hipMemcpyAsync(perm, p->perm.p, 4 * p->nvis, hipMemcpyDeviceToDevice, s), "copy perm");
+  if (fine && p->n_kept) PG_HIP(hipMemcpyAsync(fine, p->fine.p, 8 * p->n_kept, hipMemcpyDeviceToDevice, s), "copy fine");
+  if (items && p->n_items)
+    PG_HIP(hipMemcpyAsync(items, p->items.p, sizeof(Item) * p->n_items, hipMemcpyDeviceToDevice, s), "copy items");
+  return PG_OK;
+}
+
+void pg_plan_destroy(pg_plan* p) { delete p; }
+
+int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, int32_t flags, void* stream) {
+  g_error.clear();
+  int rc = check_run(p, k, vis, grid, flags, PG_ACCUMULATE | PG_FFTSHIFT);
+  if (rc != PG_OK) return rc;
+  PG_HIP(launch_grid(p, k, static_cast<const float2*>(vis), static_cast<float2*>(grid), flags,
+                     static_cast<hipStream_t>(stream)), "grid");
+  return PG_OK;
+}
+
+int pg_degrid(const pg_plan* p, const pg_kernels* k, const void* grid, void* vis_out, int32_t flags, void* stream) {
+  g_error.clear();
+  int rc = check_run(p, k, grid, vis_out, flags, PG_FFTSHIFT);
+  if (rc != PG_OK) return rc;
+  if (!grid) return fail(PG_EINVAL, "grid must be non-NULL");
+  PG_HIP(launch_degrid(p, k, static_cast<const float2*>(grid), static_cast<float2*>(vis_out), flags,
+                       static_cast<hipStream_t>(stream)), "degrid");
+  return PG_OK;
+}
+
+int pg_taper(const pg_kernels* k, const void* in, void* out, int32_t direction, double weight_sum, void* stream) {
+  g_error.clear();
+  if (!k || !in || !out) return fail(PG_EINVAL, "kernels, in and out must be non-NULL");
+  if (direction != PG_TAPER_IMAGE && direction != PG_TAPER_PREDICT) return fail(PG_EINVAL, "unknown taper direction");
+  if (direction == PG_TAPER_IMAGE && (!(weight_sum > 0.0) || !is_finite(weight_sum)))
+    return fail(PG_EINVAL, "weight_sum must be positive and finite");
+  PG_HIP(launch_taper(k, in, out, direction, weight_sum, static_cast<hipStream_t>(stream)), "taper");
+  return PG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// Device side of kernel generation (Sec. 3.2): image-domain screens
+// AA(l) AA(m) exp(-2 pi i w (n-1)) Phi_qc(l, m), their separable zero-padded DFT
+// into the oversampled uv domain (two complex float64 matrix products per
+// Mueller cell), and packing into the [phase_y][phase_x][tap_y][tap_x][q][c]
+// table the gridder reads.
+#include "common.hpp"
+
+namespace pg {
+namespace {
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__global__ void screen_kernel(const double2* __restrict__ phi, const double* __restrict__ aa, double w,
+                              double fov, int mk, int nqc, double2* __restrict__ out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (a >= mk) return;
+  const double step = fov / mk;
+  const double l = (a - mk / 2) * step, m = (b - mk / 2) * step;
+  const double r2 = l * l + m * m;
+  const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));
+  double s, c;
+  sincospi(2.0 * w * nm1, &s, &c);
+  const double g = aa[a] * aa[b];
+  const double2 scr = make_double2(g * c, -g * s);  // AA AA exp(-2 pi i w (n-1))
+  const size_t px = static_cast<size_t>(b) * mk + a;
+  const size_t npix = static_cast<size_t>(mk) * mk;
+  for (int qc = 0; qc < nqc; ++qc) out[qc * npix + px] = cmul(scr, phi[qc * npix + px]);
+}
+
+// e[di][a] = exp(+2 pi i d (a - mk/2) / (os mk)) / mk with d = di - (S os/2 - 1); the last row
+// (d = S os / 2, outside the open footprint) is zero.
+__global__ void twiddle_kernel(int support, int os, int mk, double2* __restrict__ e) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int di = blockIdx.y;
+  if (a >= mk) return;
+  const int len = support * os;
+  double2 v = make_double2(0.0, 0.0);
+  if (di < len - 1) {
+    const long long d = di - (len / 2 - 1);
+    const long long period = 2LL * os * mk;  // exp(i pi x) has period 2 in x = num / (os mk)
+    long long num = (2LL * d * (a - mk / 2)) % period;
+    if (num < 0) num += period;
+    double s, c;
+    sincospi(static_cast<double>(num) / (static_cast<double>(os) * mk), &s, &c);
+    v = make_double2(c / mk, s / mk);
+  }
+  e[static_cast<size_t>(di) * mk + a] = v;
+}
+
+// Batched complex float64 GEMM, C[m][n] = A[m][k] op(B); op(B) = B[k][n] (NN) or B[n][k]^T (NT).
+constexpr int BM = 32, BN = 32, BK = 16;
+
+template <bool BT>
+__global__ __launch_bounds__(256) void zgemm_kernel(int m, int n, int k, const double2* __restrict__ A,
+                                                    int64_t sa, const double2* __restrict__ B, int64_t sb,
+                                                    double2* __restrict__ C, int64_t sc) {
+  __shared__ double2 as[BK][BM + 1];
+  __shared__ double2 bs[BK][BN + 1];
+  const int z = blockIdx.z;
+  A += z * sa;
+  B += z * sb;
+  C += z * sc;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  double2 acc[2][2] = {};
+  for (int k0 = 0; k0 < k; k0 += BK) {
+    for (int idx = threadIdx.x; idx < BM * BK; idx += 256) {
+      int mm = idx / BK, kk = idx % BK;
+      int gm = m0 + mm, gk = k0 + kk;
+      as[kk][mm] = (gm < m && gk < k) ? A[static_cast<size_t>(gm) * k + gk] : make_double2(0.0, 0.0);
+    }
+    for (int idx = threadIdx.x; idx < BN * BK; idx += 256) {
+      int nn, kk;
+      if (BT) {
+        nn = idx / BK;
+        kk = idx % BK;
+      } else {
+        kk = idx / BN;
+        nn = idx % BN;
+      }
+      int gn = n0 + nn, gk = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (gn < n && gk < k) v = BT ? B[static_cast<size_t>(gn) * k + gk] : B[static_cast<size_t>(gk) * n + gn];
+      bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < BK; ++kk) {
+      double2 a0 = as[kk][ty], a1 = as[kk][ty + 16];
+      double2 b0 = bs[kk][tx], b1 = bs[kk][tx + 16];
+      double2 av[2] = {a0, a1}, bv[2] = {b0, b1};
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j].x = fma(av[i].x, bv[j].x, fma(-av[i].y, bv[j].y, acc[i][j].x));
+          acc[i][j].y = fma(av[i].x, bv[j].y, fma(av[i].y, bv[j].x, acc[i][j].y));
+        }
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      int gm = m0 + ty + 16 * i, gn = n0 + tx + 16 * j;
+      if (gm < m && gn < n) C[static_cast<size_t>(gm) * n + gn] = acc[i][j];
+    }
+}
+
+// table[ph_y][ph_x][t_y][t_x][qc] = T[qc][ph_y + t_y os][ph_x + t_x os]
+__global__ void pack_kernel(const double2* __restrict__ t, int support, int os, int nqc, int storage,
+                            void* __restrict__ table) {
+  const size_t len = static_cast<size_t>(support) * os;
+  const size_t total = len * len * nqc;
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    size_t qc = i % nqc;
+    size_t r = i / nqc;
+    size_t tx = r % support;
+    r /= support;
+    size_t ty = r % support;
+    r /= support;
+    size_t px = r % os;
+    size_t py = r / os;
+    double2 v = t[(qc * len + py + ty * os) * len + px + tx * os];
+    if (storage == PG_STORE_F16) {
+      // direct float64 -> float16 rounding (no intermediate float32 rounding)
+      const _Float16 re = static_cast<_Float16>(v.x), im = static_cast<_Float16>(v.y);
+      __half hr, hi;
+      __builtin_memcpy(&hr, &re, 2);
+      __builtin_memcpy(&hi, &im, 2);
+      static_cast<__half2*>(table)[i] = __halves2half2(hr, hi);
+    } else {
+      static_cast<float2*>(table)[i] = make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_screen(const double2* phi, const double* aa_lat, double w, double fov, int mk, int nqc,
+                         double2* out, hipStream_t s) {
+  dim3 grid((mk + 127) / 128, mk);
+  hipLaunchKernelGGL(screen_kernel, grid, dim3(128), 0, s, phi, aa_lat, w, fov, mk, nqc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(int support, int os, int mk, double2* e, hipStream_t s) {
+  dim3 grid((mk + 127) / 128, support * os);
+  hipLaunchKernelGGL(twiddle_kernel, grid, dim3(128), 0, s, support, os, mk, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_zgemm_nt(int batch, int m, int n, int k, const double2* a, int64_t stride_a,
+                           const double2* b, int64_t stride_b, double2* c, int64_t stride_c, hipStream_t s) {
+  dim3 grid((n + BN - 1) / BN, (m + BM - 1) / BM, batch);
+  hipLaunchKernelGGL(zgemm_kernel<true>, grid, dim3(256), 0, s, m, n, k, a, stride_a, b, stride_b, c, stride_c);
+  return hipGetLastError();
+}
+
+hipError_t launch_zgemm_nn(int batch, int m, int n, int k, const double2* a, int64_t stride_a,
+                           const double2* b, int64_t stride_b, double2* c, int64_t stride_c, hipStream_t s) {
+  dim3 grid((n + BN - 1) / BN, (m + BM - 1) / BM, batch);
+  hipLaunchKernelGGL(zgemm_kernel<false>, grid, dim3(256), 0, s, m, n, k, a, stride_a, b, stride_b, c, stride_c);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const double2* t, int support, int os, int nqc, int storage, void* table, hipStream_t s) {
+  size_t total = static_cast<size_t>(support) * os * support * os * nqc;
+  int blocks = static_cast<int>(std::min<size_t>((total + 255) / 256, 65535));
+  hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, s, t, support, os, nqc, storage, table);
+  return hipGetLastError();
+}
+
+}  // namespace pg

@@ -1,0 +1,292 @@
+"""ctypes binding of libpolgrid.so (the C ABI in include/polgrid.h).
+
+Argument marshalling only: device buffers are torch tensors on the current HIP
+device, streams are torch's current stream, and every step of the path runs in
+the library's HIP kernels.  torch.fft (rocFFT) moves between grid and image.
+There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpolgrid.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+KIND_GRID, KIND_DEGRID = 0, 1
+STORE_F32, STORE_F16 = 0, 1
+STOKES_IAU, STOKES_PAPER = 0, 1
+ACCUMULATE, FFTSHIFT = 1, 2
+TAPER_IMAGE, TAPER_PREDICT = 0, 1
+
+
+class PgGeometry(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("cell", c_double), ("os", c_int32), ("nplanes", c_int32),
+                ("w_planes", POINTER(c_double)), ("support", POINTER(c_int32)), ("tile", POINTER(c_int32)),
+                ("aa_support", c_int32), ("mk", c_int32)]
+
+
+class PgKernelSpec(ctypes.Structure):
+    _fields_ = [("g", PgGeometry), ("npol", c_int32), ("kind", c_int32), ("jones", POINTER(c_double)),
+                ("eps_null", c_double), ("stokes_convention", c_int32), ("storage", c_int32)]
+
+
+class PgKernelsDesc(ctypes.Structure):
+    _fields_ = [("npol", c_int32), ("kind", c_int32), ("storage", c_int32), ("os", c_int32), ("n", c_int32),
+                ("nplanes", c_int32), ("table", c_void_p), ("plane_offset", POINTER(c_int64)),
+                ("aa_pixels", POINTER(c_double))]
+
+
+class PgPlanDesc(ctypes.Structure):
+    _fields_ = [("nvis", c_int64), ("n_kept", c_int64), ("n_dropped", c_int64), ("n_items", c_int64),
+                ("perm", c_void_p), ("fine", c_void_p), ("items", c_void_p)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
+
+EXPORTS = {
+    "pg_version": (c_int, []),
+    "pg_last_error": (ctypes.c_char_p, []),
+    "pg_set_allocator": (None, [ALLOC_FN, FREE_FN, c_void_p]),
+    "pg_make_kernels": (c_int, [POINTER(PgKernelSpec), c_void_p, POINTER(c_void_p)]),
+    "pg_kernels_info": (c_int, [c_void_p, POINTER(PgKernelsDesc)]),
+    "pg_kernels_copy_table": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "pg_kernels_destroy": (None, [c_void_p]),
+    "pg_plan_create": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, POINTER(c_void_p), POINTER(c_int64)]),
+    "pg_plan_info": (c_int, [c_void_p, POINTER(PgPlanDesc)]),
+    "pg_plan_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pg_plan_destroy": (None, [c_void_p]),
+    "pg_grid": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "pg_degrid": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "pg_taper": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]),
+}
+
+_lib = None
+
+
+class PolgridError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"polgrid error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_2206_15117_amd.build)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise PolgridError(rc, lib().pg_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+_alloc_refs = []
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device allocations through torch's caching allocator."""
+    import torch
+
+    if not enable:
+        lib().pg_set_allocator(ALLOC_FN(), FREE_FN(), None)
+        _alloc_refs.clear()
+        return
+
+    def _alloc(size, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(size), stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a, f = ALLOC_FN(_alloc), FREE_FN(_free)
+    _alloc_refs[:] = [a, f]
+    lib().pg_set_allocator(a, f, None)
+
+
+def _geometry_struct(geom):
+    w = np.ascontiguousarray(geom.w_planes, dtype=np.float64)
+    s = np.ascontiguousarray(geom.support, dtype=np.int32)
+    t = np.ascontiguousarray(geom.tile, dtype=np.int32)
+    g = PgGeometry(int(geom.n), float(geom.cell), int(geom.os), int(w.shape[0]),
+                   w.ctypes.data_as(POINTER(c_double)), s.ctypes.data_as(POINTER(c_int32)),
+                   t.ctypes.data_as(POINTER(c_int32)), int(geom.aa_support), int(geom.mk))
+    return g, (w, s, t)
+
+
+class Kernels:
+    """A kernel table set (pg_kernels)."""
+
+    def __init__(self, handle, geom):
+        self._h = handle
+        self.geom = geom
+        d = PgKernelsDesc()
+        _check(lib().pg_kernels_info(self._h, ctypes.byref(d)))
+        self.npol, self.kind, self.storage = d.npol, d.kind, d.storage
+        self.os, self.n, self.nplanes = d.os, d.n, d.nplanes
+        self.plane_offset = np.array([d.plane_offset[i] for i in range(d.nplanes + 1)], dtype=np.int64)
+        self.aa_pixels = np.array([d.aa_pixels[i] for i in range(d.n)])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def table(self):
+        """Device copy of the whole table: complex64 (F32) or float16 pairs [entries, 2] (F16)."""
+        import torch
+
+        n = int(self.plane_offset[-1])
+        if self.storage == STORE_F16:
+            out = torch.empty((n, 2), dtype=torch.float16, device="cuda")
+        else:
+            out = torch.empty(n, dtype=torch.complex64, device="cuda")
+        _check(lib().pg_kernels_copy_table(self._h, _ptr(out), _stream()))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pg_kernels_destroy(self._h)
+            self._h = None
+
+
+def make_kernels(geom, npol: int, kind: int = KIND_GRID, jones=None, eps_null: float = 0.2,
+                 storage: int = STORE_F32, convention: int = STOKES_IAU, stream=None) -> Kernels:
+    g, keep = _geometry_struct(geom)
+    jp = None
+    if jones is not None:
+        jarr = np.ascontiguousarray(jones, dtype=np.complex128)
+        if jarr.shape != (2, 2, geom.mk, geom.mk):
+            raise ValueError(f"jones must be complex128 [2][2][mk][mk], got {jarr.shape}")
+        keep = keep + (jarr,)
+        jp = jarr.ctypes.data_as(POINTER(c_double))
+    spec = PgKernelSpec(g, int(npol), int(kind), jp, float(eps_null), int(convention), int(storage))
+    h = c_void_p()
+    _check(lib().pg_make_kernels(ctypes.byref(spec), _stream(stream), ctypes.byref(h)))
+    return Kernels(h, geom)
+
+
+class Plan:
+    """Binned visibilities (pg_plan)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        d = PgPlanDesc()
+        _check(lib().pg_plan_info(self._h, ctypes.byref(d)))
+        self.nvis, self.n_kept, self.n_dropped, self.n_items = d.nvis, d.n_kept, d.n_dropped, d.n_items
+
+    @property
+    def handle(self):
+        return self._h
+
+    def arrays(self):
+        """(perm [nvis], fine [n_kept, 2], items [n_items, 8]) as int32 device tensors."""
+        import torch
+
+        perm = torch.empty(max(self.nvis, 1), dtype=torch.int32, device="cuda")
+        fine = torch.empty((max(self.n_kept, 1), 2), dtype=torch.int32, device="cuda")
+        items = torch.empty((max(self.n_items, 1), 8), dtype=torch.int32, device="cuda")
+        _check(lib().pg_plan_copy(self._h, _ptr(perm), _ptr(fine), _ptr(items), _stream()))
+        return perm[:self.nvis], fine[:self.n_kept], items[:self.n_items]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pg_plan_destroy(self._h)
+            self._h = None
+
+
+def plan(kernels: Kernels, uvw, max_chunk: int = 1024, stream=None) -> Plan:
+    import torch
+
+    if uvw.dtype != torch.float64 or uvw.dim() != 2 or uvw.shape[1] != 3 or not uvw.is_contiguous():
+        raise ValueError("uvw must be a contiguous float64 [nvis, 3] device tensor")
+    h = c_void_p()
+    nd = c_int64()
+    _check(lib().pg_plan_create(kernels.handle, _ptr(uvw), uvw.shape[0], int(max_chunk), _stream(stream),
+                                ctypes.byref(h), ctypes.byref(nd)))
+    return Plan(h)
+
+
+def _grid_shape(k: Kernels):
+    return (k.npol, k.n, k.n)
+
+
+def grid(p: Plan, k: Kernels, vis, out=None, accumulate: bool = False, fftshift: bool = False, stream=None):
+    import torch
+
+    if vis.dtype != torch.complex64 or not vis.is_contiguous() or tuple(vis.shape) != (p.nvis, k.npol):
+        raise ValueError(f"vis must be contiguous complex64 [{p.nvis}, {k.npol}]")
+    if out is None:
+        out = torch.empty(_grid_shape(k), dtype=torch.complex64, device=vis.device)
+    elif out.dtype != torch.complex64 or tuple(out.shape) != _grid_shape(k) or not out.is_contiguous():
+        raise ValueError("out must be contiguous complex64 [npol, n, n]")
+    flags = (ACCUMULATE if accumulate else 0) | (FFTSHIFT if fftshift else 0)
+    _check(lib().pg_grid(p.handle, k.handle, _ptr(vis), _ptr(out), flags, _stream(stream)))
+    return out
+
+
+def degrid(p: Plan, k: Kernels, g, out=None, fftshift: bool = False, stream=None):
+    import torch
+
+    if g.dtype != torch.complex64 or tuple(g.shape) != _grid_shape(k) or not g.is_contiguous():
+        raise ValueError("grid must be contiguous complex64 [npol, n, n]")
+    if out is None:
+        out = torch.empty((p.nvis, k.npol), dtype=torch.complex64, device=g.device)
+    elif out.dtype != torch.complex64 or tuple(out.shape) != (p.nvis, k.npol) or not out.is_contiguous():
+        raise ValueError("out must be contiguous complex64 [nvis, npol]")
+    _check(lib().pg_degrid(p.handle, k.handle, _ptr(g), _ptr(out), FFTSHIFT if fftshift else 0, _stream(stream)))
+    return out
+
+
+def taper(k: Kernels, inp, out, direction: int, weight_sum: float = 1.0, stream=None):
+    _check(lib().pg_taper(k.handle, _ptr(inp), _ptr(out), int(direction), float(weight_sum), _stream(stream)))
+    return out
+
+
+def image(p: Plan, k: Kernels, vis, weight_sum: float, grid_buf=None, out=None):
+    """Dirty image: grid (centring folded in) -> FFT (rocFFT via torch) -> taper correction."""
+    import torch
+
+    g = grid(p, k, vis, out=grid_buf, fftshift=True)
+    f = torch.fft.fft2(g)
+    if out is None:
+        out = torch.empty(_grid_shape(k), dtype=torch.float32, device=vis.device)
+    return taper(k, f, out, TAPER_IMAGE, weight_sum)
+
+
+def predict(p: Plan, k: Kernels, model, out=None, buf=None):
+    """Model visibilities: taper correction -> unnormalised inverse FFT -> degrid."""
+    import torch
+
+    if buf is None:
+        buf = torch.empty(_grid_shape(k), dtype=torch.complex64, device=model.device)
+    taper(k, model, buf, TAPER_PREDICT)
+    g = torch.fft.ifft2(buf, norm="forward")
+    return degrid(p, k, g, out=out, fftshift=True)
