@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--max-chunk", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=40000)
+    ap.add_argument("--grid-variant", choices=["auto", "atomic", "banded"], default="auto")
     return ap.parse_args()
 
 
@@ -73,6 +74,7 @@ def main():
 
     torch.cuda.set_device(0)
     pg.use_torch_allocator(True)
+    variant = {"auto": 0, "atomic": pg.VARIANT_ATOMIC, "banded": pg.VARIANT_BANDED}[args.grid_variant]
     w = synth.config2(nvis=args.nvis)
     g = w.geom
     jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
@@ -109,7 +111,7 @@ def main():
         p = pg.plan(kg, uvw, max_chunk=args.max_chunk)
         if record:
             e[1].record()
-        pg.grid(p, kg, vis, out=grid_buf, fftshift=True)
+        pg.grid(p, kg, vis, out=grid_buf, fftshift=True, variant=variant)
         if record:
             e[2].record()
         f = torch.fft.fft2(grid_buf)

@@ -70,6 +70,10 @@ extern "C" {
 #define PG_ACCUMULATE 1 /* pg_grid: add onto the existing grid instead of overwriting it */
 #define PG_FFTSHIFT 2   /* the grid in memory is G(X,Y) (-1)^(X+Y): the centring modulation
                            the FFT needs is folded into the grid flush / degrid gather */
+#define PG_VARIANT_ATOMIC 4 /* pg_grid: force the LDS-atomic accumulation kernel */
+#define PG_VARIANT_BANDED 8 /* pg_grid: force the row-band ownership kernel (no LDS atomics);
+                               without either flag the library picks by sub-grid width.
+                               Both give the same result up to float32 summation order. */
 
 /* pg_taper directions */
 #define PG_TAPER_IMAGE 0   /* complex FFT output -> real image / (AA(l) AA(m)) / weight_sum */
@@ -82,7 +86,9 @@ typedef struct pg_geometry {
   int32_t nplanes;         /* number of w-planes, 1 .. 1024 */
   const double* w_planes;  /* host [nplanes], ascending, wavelengths */
   const int32_t* support;  /* host [nplanes], taps per axis, 1 .. 64 */
-  const int32_t* tile;     /* host [nplanes], uv tile side used to bin visibilities, >= 1 */
+  const int32_t* tile;     /* host [nplanes], uv tile side used to bin visibilities, >= 1; the
+                              sub-grid (tile + support - 1) rows x pitch x npol x 8 B must fit
+                              162688 B of LDS, pitch = the width rounded up to == support mod 32 */
   int32_t aa_support;      /* support of the prolate spheroidal anti-aliasing function (7) */
   int32_t mk;              /* samples per side of the image lattice kernels are built on (even) */
 } pg_geometry;
@@ -104,9 +110,11 @@ typedef struct pg_plan pg_plan;
 /* Read-only view of a kernel set, for inspection and tests. */
 typedef struct pg_kernels_desc {
   int32_t npol, kind, storage, os, n, nplanes;
-  const void* table;            /* device; per plane [os][os][S][S][npol][npol] entries
-                                   (phase_y, phase_x, tap_y, tap_x, q, c); tap t of phase ph
-                                   has fine-grid offset ph - S os/2 + 1 + t os */
+  const void* table;            /* device; per plane [os][os][npol^2/E][S][S][E] entries
+                                   (phase_y, phase_x, chunk, tap_y, tap_x, e) with Mueller cell
+                                   q * npol + c = chunk * E + e, E = min(npol^2, 2) for F32 and
+                                   min(npol^2, 4) for F16 (one 16-byte chunk per tap); tap t of
+                                   phase ph has fine-grid offset ph - S os/2 + 1 + t os */
   const int64_t* plane_offset;  /* host [nplanes + 1], offsets into table in entries */
   const double* aa_pixels;      /* host [n], anti-aliasing function at the image pixels */
 } pg_kernels_desc;
@@ -138,7 +146,7 @@ void pg_set_allocator(void* (*alloc_fn)(size_t, void*, void*),
  * the mk x mk lattice, restricted to offsets |d| < S_p os / 2.  Host float64
  * Mueller algebra, device float64 transforms, stored in spec->storage.
  * Synchronises `stream`.  Errors: PG_EINVAL (bad spec), PG_EUNSUPPORTED (sub-grid
- * of some plane larger than the LDS budget), PG_ENOMEM, PG_EHIP. */
+ * of some plane larger than the 162688-byte LDS budget), PG_ENOMEM, PG_EHIP. */
 int pg_make_kernels(const pg_kernel_spec* spec, void* stream, pg_kernels** out);
 int pg_kernels_info(const pg_kernels* k, pg_kernels_desc* out);
 /* Copy the whole table (plane_offset[nplanes] entries of 8 bytes (F32) or 4 bytes (F16)) into

@@ -17,7 +17,7 @@ namespace {
 thread_local std::string g_error;
 std::mutex g_alloc_mu;
 Allocator g_alloc;
-constexpr size_t kLdsBudget = 160 * 1024;
+constexpr size_t kLdsBudget = 160 * 1024 - 1152;  // sub-grid share of the 160 KiB; the rest is gridder scratch
 
 int fail(int code, const std::string& msg) {
   g_error = msg;
@@ -49,9 +49,10 @@ int check_geometry(const pg_geometry& g, int npol) {
     if (g.support[p] < 1 || g.support[p] > 64) return fail(PG_EINVAL, "support must be in [1, 64]");
     if (g.support[p] > g.n) return fail(PG_EINVAL, "support must not exceed n");
     if (g.tile[p] < 1 || g.tile[p] > g.n) return fail(PG_EINVAL, "tile must be in [1, n]");
-    const size_t w = static_cast<size_t>(g.tile[p]) + g.support[p] - 1;
-    if (w * w * npol * 8 > kLdsBudget)
-      return fail(PG_EUNSUPPORTED, "plane " + std::to_string(p) + ": sub-grid (tile + support - 1)^2 x npol x 8 B exceeds 160 KiB of LDS");
+    const int w = g.tile[p] + g.support[p] - 1;
+    if (static_cast<size_t>(w) * lds_pitch(w, g.support[p]) * npol * 8 > kLdsBudget)
+      return fail(PG_EUNSUPPORTED, "plane " + std::to_string(p) +
+                                       ": sub-grid (tile + support - 1) rows x padded pitch x npol x 8 B exceeds 158.875 KiB of LDS");
   }
   if (g.aa_support < 1 || g.aa_support > 64) return fail(PG_EINVAL, "aa_support must be in [1, 64]");
   if (g.mk < 2 || g.mk > 4096 || (g.mk & 1)) return fail(PG_EINVAL, "mk must be even and in [2, 4096]");
@@ -114,11 +115,11 @@ int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** ou
     pinfo[p].support = g.support[p];
     pinfo[p].tile = g.tile[p];
     pinfo[p].width = g.tile[p] + g.support[p] - 1;
-    pinfo[p].pad = 0;
+    pinfo[p].pitch = lds_pitch(pinfo[p].width, g.support[p]);
     k->max_width = std::max(k->max_width, pinfo[p].width);
+    k->lds_bytes = std::max(k->lds_bytes, static_cast<size_t>(pinfo[p].width) * pinfo[p].pitch * np * 8);
     smax = std::max(smax, g.support[p]);
   }
-  k->lds_bytes = static_cast<size_t>(k->max_width) * k->max_width * np * 8;
 
   // Anti-aliasing function on the kernel lattice and at the image pixels.
   const double c = M_PI * g.aa_support / 2.0;
@@ -337,7 +338,8 @@ void pg_plan_destroy(pg_plan* p) { delete p; }
 
 int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, int32_t flags, void* stream) {
   g_error.clear();
-  int rc = check_run(p, k, vis, grid, flags, PG_ACCUMULATE | PG_FFTSHIFT);
+  int rc = check_run(p, k, vis, grid, flags, PG_ACCUMULATE | PG_FFTSHIFT | PG_VARIANT_ATOMIC | PG_VARIANT_BANDED);
+  if ((flags & PG_VARIANT_ATOMIC) && (flags & PG_VARIANT_BANDED)) return fail(PG_EINVAL, "choose one grid variant");
   if (rc != PG_OK) return rc;
   PG_HIP(launch_grid(p, k, static_cast<const float2*>(vis), static_cast<float2*>(grid), flags,
                      static_cast<hipStream_t>(stream)), "grid");

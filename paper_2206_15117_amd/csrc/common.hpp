@@ -27,8 +27,18 @@ struct PlaneInfo {
   int32_t support;  // S
   int32_t tile;     // T
   int32_t width;    // sub-grid side T + S - 1
-  int32_t pad;
+  int32_t pitch;    // LDS row pitch in complex elements, >= width, == S (mod 32)
 };
+
+// LDS row pitch of a sub-grid row: the footprint rows a wave touches are S apart in tap order,
+// so a pitch congruent to S modulo 32 complex elements keeps 64 consecutive taps on distinct banks.
+inline int lds_pitch(int width, int support) { return width + (((support - width) % 32) + 32) % 32; }
+
+// Table entries per load chunk: two complex64 (16 B) or four float16 pairs (16 B), capped by npol^2.
+inline int chunk_entries(int storage, int nqc) {
+  const int e = storage == PG_STORE_F16 ? 4 : 2;
+  return nqc < e ? nqc : e;
+}
 
 void set_error(const std::string& msg);
 

@@ -4,9 +4,12 @@
 // stage) with 4x4 Mueller kernels.  One workgroup takes one work item: a chunk
 // of visibilities that share a w-plane and a uv tile (binned by the plan,
 // phase-sorted inside the tile so neighbouring visibilities reuse table lines
-// in cache).  The tile's sub-grid of (T + S - 1)^2 points x npol lives in LDS,
-// planar [q][re|im][y][x] so the 64 lanes of a wave, which walk consecutive
-// taps of one visibility, hit consecutive banks.
+// in cache).  The tile's sub-grid of (T + S - 1)^2 points x npol lives in LDS
+// with a row pitch congruent to S modulo 32 complex elements, so the 64 lanes of
+// a wave, which walk consecutive taps of one visibility across footprint rows,
+// hit distinct banks.  Table taps are stored chunk-major per phase
+// ([chunk][tap][e]), so each 16-byte load of 64 consecutive taps is one
+// contiguous 1 KiB block.
 //   grid:   each wave takes one visibility at a time; lane t owns tap t; the
 //           npol x npol Mueller product is done in registers and added into
 //           the LDS sub-grid with LDS float atomics (waves overlap); the
@@ -20,45 +23,63 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
+constexpr size_t kBandScratch = (256 + 32) * sizeof(int);  // row loads and band bounds of the banded grid
 
 __device__ inline int ceil_div_i(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
 
-template <int NQC>
-__device__ inline void load_taps(const float2* __restrict__ p, float2 (&t)[NQC]) {
-  if constexpr (NQC % 2 == 0) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int i = 0; i < NQC / 2; ++i) {
-      const float4 v = q[i];
-      t[2 * i] = make_float2(v.x, v.y);
-      t[2 * i + 1] = make_float2(v.z, v.w);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NQC; ++i) t[i] = p[i];
-  }
+// Per-visibility metadata is the same for all lanes of a wave; keeping it in scalar registers lets
+// the tap loads use a scalar base address plus one 32-bit lane offset.
+__device__ inline int2 uniform(int2 v) {
+  return make_int2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y));
 }
 
-template <int NQC>
-__device__ inline void load_taps(const __half2* __restrict__ p, float2 (&t)[NQC]) {
-  if constexpr (NQC % 4 == 0) {
-    const uint4* q = reinterpret_cast<const uint4*>(p);
+template <typename TapT>
+struct Chunk;
+template <>
+struct Chunk<float2> {
+  static constexpr int E = 2;  // complex64 entries per 16-byte chunk
+};
+template <>
+struct Chunk<__half2> {
+  static constexpr int E = 4;  // float16 pairs per 16-byte chunk
+};
+
+template <int NQC, typename TapT>
+struct TapChunks {
+  static constexpr int E = NQC < Chunk<TapT>::E ? NQC : Chunk<TapT>::E;
+  static constexpr int NCH = NQC / E;
+  const TapT* base[NCH];  // wave-uniform: chunk j of one phase block [chunk][SS][E]
+  __device__ TapChunks(const TapT* ph, int ss) {
 #pragma unroll
-    for (int i = 0; i < NQC / 4; ++i) {
-      const uint4 v = q[i];
-      const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    for (int j = 0; j < NCH; ++j) base[j] = ph + static_cast<size_t>(j) * ss * E;
+  }
+  // All npol^2 taps of tap index t (a per-lane 32-bit offset from uniform chunk bases).
+  __device__ void load(uint32_t t, float2 (&out)[NQC]) const {
+    const uint32_t boff = t * static_cast<uint32_t>(E * sizeof(TapT));  // 32-bit lane offset
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        __half2 h;
-        __builtin_memcpy(&h, &w[j], 4);
-        t[4 * i + j] = __half22float2(h);
+    for (int j = 0; j < NCH; ++j) {
+      const TapT* p = reinterpret_cast<const TapT*>(reinterpret_cast<const char*>(base[j]) + boff);
+      if constexpr (E == 2) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        out[2 * j] = make_float2(v.x, v.y);
+        out[2 * j + 1] = make_float2(v.z, v.w);
+      } else if constexpr (E == 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(p);
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          __half2 h;
+          __builtin_memcpy(&h, &w[e], 4);
+          out[4 * j + e] = __half22float2(h);
+        }
+      } else if constexpr (sizeof(TapT) == 8) {
+        out[j] = *reinterpret_cast<const float2*>(p);
+      } else {
+        out[j] = __half22float2(*reinterpret_cast<const __half2*>(p));
       }
     }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NQC; ++i) t[i] = __half22float2(p[i]);
   }
-}
+};
 
 template <int NP, typename TapT>
 __global__ __launch_bounds__(kThreads) void grid_kernel(const Item* __restrict__ items, const int2* __restrict__ fine,
@@ -67,30 +88,30 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(const Item* __restrict__
                                                         const TapT* __restrict__ table,
                                                         const PlaneInfo* __restrict__ planes, int os, int n,
                                                         float2* __restrict__ grid, int flags) {
-  extern __shared__ float lds[];
+  extern __shared__ float lds[];  // [q][re|im][W][P]
   const Item it = items[blockIdx.x];
   const PlaneInfo pl = planes[it.plane];
-  const int S = pl.support, W = pl.width, WW = W * W, SS = S * S, half = S * os / 2;
+  const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
   const float inv_s = 1.0f / static_cast<float>(S);
-  for (int i = threadIdx.x; i < 2 * NP * WW; i += kThreads) lds[i] = 0.0f;
+  for (int i = threadIdx.x; i < 2 * NP * WP; i += kThreads) lds[i] = 0.0f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = it.start + wave; i < it.end; i += kWaves) {
-    const int2 f = fine[i];
-    const int k = perm[i];
+    const int2 f = uniform(fine[i]);
+    const int k = __builtin_amdgcn_readfirstlane(perm[i]);
     const int x0 = ceil_div_i(f.x - half + 1, os), y0 = ceil_div_i(f.y - half + 1, os);
     const int phx = x0 * os - f.x + half - 1, phy = y0 * os - f.y + half - 1;
     float2 v[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) v[c] = vis[static_cast<size_t>(k) * NP + c];
-    const TapT* base = table + pl.offset + static_cast<size_t>(phy * os + phx) * SS * NP * NP;
+    const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(phy * os + phx) * SS * NP * NP, SS);
     const int lx = x0 - it.ox, ly = y0 - it.oy;
     for (int t = lane; t < SS; t += 64) {
       const int ty = static_cast<int>((static_cast<float>(t) + 0.5f) * inv_s);
       const int tx = t - ty * S;
       float2 tap[NP * NP];
-      load_taps<NP * NP>(base + static_cast<size_t>(t) * NP * NP, tap);
-      const int off = (ly + ty) * W + lx + tx;
+      tc.load(static_cast<uint32_t>(t), tap);
+      const int off = (ly + ty) * P + lx + tx;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         float re = 0.0f, im = 0.0f;
@@ -100,26 +121,162 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(const Item* __restrict__
           re = fmaf(a.x, v[c].x, fmaf(-a.y, v[c].y, re));
           im = fmaf(a.x, v[c].y, fmaf(a.y, v[c].x, im));
         }
-        atomicAdd(&lds[(2 * q) * WW + off], re);
-        atomicAdd(&lds[(2 * q + 1) * WW + off], im);
+        atomicAdd(&lds[(2 * q) * WP + off], re);
+        atomicAdd(&lds[(2 * q + 1) * WP + off], im);
       }
     }
   }
   __syncthreads();
   const bool shift = (flags & PG_FFTSHIFT) != 0;
   const size_t pstride = static_cast<size_t>(n) * n;
-  for (int idx = threadIdx.x; idx < WW; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < W * W; idx += kThreads) {
     const int y = idx / W, x = idx - y * W;
     const int X = it.ox + x, Y = it.oy + y;
     if (X >= n || Y >= n) continue;
+    const int l = y * P + x;
     const float sg = (shift && ((X + Y) & 1)) ? -1.0f : 1.0f;
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      const float re = lds[(2 * q) * WW + idx], im = lds[(2 * q + 1) * WW + idx];
+      const float re = lds[(2 * q) * WP + l], im = lds[(2 * q + 1) * WP + l];
       if (re != 0.0f || im != 0.0f) {
         float* g = reinterpret_cast<float*>(grid + q * pstride + static_cast<size_t>(Y) * n + X);
         unsafeAtomicAdd(g, sg * re);
         unsafeAtomicAdd(g + 1, sg * im);
+      }
+    }
+  }
+}
+
+// Banded variant: the sub-grid rows are split into kWaves contiguous bands of equal load (rows
+// weighted by how many footprints of the item cover them); wave w owns band w and walks every
+// visibility of the item, taking only the footprint rows inside its band.  Bands are disjoint, so
+// the sub-grid (complex [q][W][P] in LDS) is updated with plain read-modify-write, no LDS atomics.
+template <int NP, typename TapT>
+__global__ __launch_bounds__(kThreads) void grid_banded_kernel(const Item* __restrict__ items,
+                                                               const int2* __restrict__ fine,
+                                                               const int32_t* __restrict__ perm,
+                                                               const float2* __restrict__ vis,
+                                                               const TapT* __restrict__ table,
+                                                               const PlaneInfo* __restrict__ planes, int os, int n,
+                                                               float2* __restrict__ grid, int flags, int sub_bytes) {
+  extern __shared__ float lds_f[];
+  float2* lds = reinterpret_cast<float2*>(lds_f);
+  int* rowload = reinterpret_cast<int*>(reinterpret_cast<char*>(lds_f) + sub_bytes);  // [W + 1]
+  int* band = rowload + 256;                                                             // [kWaves + 1]
+  const Item it = items[blockIdx.x];
+  const PlaneInfo pl = planes[it.plane];
+  const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
+  const float inv_s = 1.0f / static_cast<float>(S);
+  for (int i = threadIdx.x; i < NP * WP; i += kThreads) lds[i] = make_float2(0.0f, 0.0f);
+  for (int i = threadIdx.x; i <= W; i += kThreads) rowload[i] = 0;
+  __syncthreads();
+  // coverage count of every sub-grid row (difference array, then a prefix sum in one wave)
+  for (int i = it.start + static_cast<int>(threadIdx.x); i < it.end; i += kThreads) {
+    const int ly = ceil_div_i(fine[i].y - half + 1, os) - it.oy;
+    atomicAdd(&rowload[ly], 1);
+    atomicAdd(&rowload[ly + S], -1);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    int carry = 0;
+    for (int r0 = 0; r0 < W; r0 += 64) {  // inclusive prefix sums: coverage, then cumulative load
+      int c = (r0 + lane < W) ? rowload[r0 + lane] : 0;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(c, d, 64);
+        if (lane >= d) c += o;
+      }
+      c += carry;
+      carry = __shfl(c, 63, 64);
+      if (r0 + lane < W) rowload[r0 + lane] = c;
+    }
+    __builtin_amdgcn_wave_barrier();
+    carry = 0;
+    for (int r0 = 0; r0 < W; r0 += 64) {
+      int c = (r0 + lane < W) ? rowload[r0 + lane] : 0;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(c, d, 64);
+        if (lane >= d) c += o;
+      }
+      c += carry;
+      carry = __shfl(c, 63, 64);
+      if (r0 + lane < W) rowload[r0 + lane] = c;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // band w starts at the first row whose cumulative load reaches w / kWaves of the total
+    if (lane <= kWaves) {
+      const long long total = rowload[W - 1];
+      int r = 0;
+      if (lane == kWaves) {
+        r = W;
+      } else if (lane > 0) {
+        const long long thr = (total * lane + kWaves - 1) / kWaves;
+        while (r < W && rowload[r] < thr) ++r;
+        ++r;
+        if (r > W) r = W;
+      }
+      band[lane] = r;
+    }
+  }
+  __syncthreads();
+  const int r0 = band[wave], r1 = band[wave + 1];
+  int2 f = uniform(it.start < it.end ? fine[it.start] : make_int2(0, 0));
+  for (int i = it.start; i < it.end && r0 < r1; ++i) {
+    const int2 fn = uniform((i + 1 < it.end) ? fine[i + 1] : f);  // next metadata in flight early
+    const int y0 = ceil_div_i(f.y - half + 1, os);
+    const int ly = y0 - it.oy;
+    const int a = max(ly, r0), b = min(ly + S, r1);
+    if (a < b) {
+      const int x0 = ceil_div_i(f.x - half + 1, os);
+      const int phx = x0 * os - f.x + half - 1, phy = y0 * os - f.y + half - 1;
+      const int k = __builtin_amdgcn_readfirstlane(perm[i]);
+      float2 v[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) v[c] = vis[static_cast<size_t>(k) * NP + c];
+      const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(phy * os + phx) * SS * NP * NP, SS);
+      const int lx = x0 - it.ox;
+      const int cnt = (b - a) * S;
+      const uint32_t t0 = static_cast<uint32_t>((a - ly) * S);
+#pragma unroll 2
+      for (int u = lane; u < cnt; u += 64) {
+        const int rr = static_cast<int>((static_cast<float>(u) + 0.5f) * inv_s);
+        const int tx = u - rr * S;
+        float2 tap[NP * NP];
+        tc.load(t0 + static_cast<uint32_t>(u), tap);
+        const int off = (a + rr) * P + lx + tx;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          float2 g = lds[q * WP + off];
+#pragma unroll
+          for (int c = 0; c < NP; ++c) {
+            const float2 t2 = tap[q * NP + c];
+            g.x = fmaf(t2.x, v[c].x, fmaf(-t2.y, v[c].y, g.x));
+            g.y = fmaf(t2.x, v[c].y, fmaf(t2.y, v[c].x, g.y));
+          }
+          lds[q * WP + off] = g;
+        }
+      }
+    }
+    f = fn;
+  }
+  __syncthreads();
+  const bool shift = (flags & PG_FFTSHIFT) != 0;
+  const size_t pstride = static_cast<size_t>(n) * n;
+  for (int idx = threadIdx.x; idx < W * W; idx += kThreads) {
+    const int y = idx / W, x = idx - y * W;
+    const int X = it.ox + x, Y = it.oy + y;
+    if (X >= n || Y >= n) continue;
+    const int l = y * P + x;
+    const float sg = (shift && ((X + Y) & 1)) ? -1.0f : 1.0f;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const float2 g = lds[q * WP + l];
+      if (g.x != 0.0f || g.y != 0.0f) {
+        float* gp = reinterpret_cast<float*>(grid + q * pstride + static_cast<size_t>(Y) * n + X);
+        unsafeAtomicAdd(gp, sg * g.x);
+        unsafeAtomicAdd(gp + 1, sg * g.y);
       }
     }
   }
@@ -133,51 +290,52 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(const Item* __restrict
                                                           const PlaneInfo* __restrict__ planes, int os, int n,
                                                           const float2* __restrict__ grid,
                                                           float2* __restrict__ vis_out, int flags) {
-  extern __shared__ float lds[];
+  extern __shared__ float lds_f[];
+  float2* lds = reinterpret_cast<float2*>(lds_f);  // [q][W][P]
   const Item it = items[blockIdx.x];
   const PlaneInfo pl = planes[it.plane];
-  const int S = pl.support, W = pl.width, WW = W * W, SS = S * S, half = S * os / 2;
+  const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
   const float inv_s = 1.0f / static_cast<float>(S);
   const bool shift = (flags & PG_FFTSHIFT) != 0;
   const size_t pstride = static_cast<size_t>(n) * n;
-  for (int idx = threadIdx.x; idx < WW; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < W * W; idx += kThreads) {
     const int y = idx / W, x = idx - y * W;
     const int X = it.ox + x, Y = it.oy + y;
     const bool in = X < n && Y < n;
     const float sg = (shift && ((X + Y) & 1)) ? -1.0f : 1.0f;
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      float2 g = in ? grid[q * pstride + static_cast<size_t>(Y) * n + X] : make_float2(0.0f, 0.0f);
-      lds[(2 * q) * WW + idx] = sg * g.x;
-      lds[(2 * q + 1) * WW + idx] = sg * g.y;
+      const float2 g = in ? grid[q * pstride + static_cast<size_t>(Y) * n + X] : make_float2(0.0f, 0.0f);
+      lds[q * WP + y * P + x] = make_float2(sg * g.x, sg * g.y);
     }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = it.start + wave; i < it.end; i += kWaves) {
-    const int2 f = fine[i];
-    const int k = perm[i];
+    const int2 f = uniform(fine[i]);
+    const int k = __builtin_amdgcn_readfirstlane(perm[i]);
     const int x0 = ceil_div_i(f.x - half + 1, os), y0 = ceil_div_i(f.y - half + 1, os);
     const int phx = x0 * os - f.x + half - 1, phy = y0 * os - f.y + half - 1;
-    const TapT* base = table + pl.offset + static_cast<size_t>(phy * os + phx) * SS * NP * NP;
+    const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(phy * os + phx) * SS * NP * NP, SS);
     const int lx = x0 - it.ox, ly = y0 - it.oy;
     float acc[2 * NP];
 #pragma unroll
     for (int c = 0; c < 2 * NP; ++c) acc[c] = 0.0f;
+#pragma unroll 2
     for (int t = lane; t < SS; t += 64) {
       const int ty = static_cast<int>((static_cast<float>(t) + 0.5f) * inv_s);
       const int tx = t - ty * S;
       float2 tap[NP * NP];
-      load_taps<NP * NP>(base + static_cast<size_t>(t) * NP * NP, tap);
-      const int off = (ly + ty) * W + lx + tx;
+      tc.load(static_cast<uint32_t>(t), tap);
+      const int off = (ly + ty) * P + lx + tx;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        const float gr = lds[(2 * q) * WW + off], gi = lds[(2 * q + 1) * WW + off];
+        const float2 g = lds[q * WP + off];
 #pragma unroll
         for (int c = 0; c < NP; ++c) {
           const float2 a = tap[q * NP + c];  // conj(a) * g
-          acc[2 * c] = fmaf(a.x, gr, fmaf(a.y, gi, acc[2 * c]));
-          acc[2 * c + 1] = fmaf(a.x, gi, fmaf(-a.y, gr, acc[2 * c + 1]));
+          acc[2 * c] = fmaf(a.x, g.x, fmaf(a.y, g.y, acc[2 * c]));
+          acc[2 * c + 1] = fmaf(a.x, g.y, fmaf(-a.y, g.x, acc[2 * c + 1]));
         }
       }
     }
@@ -236,6 +394,21 @@ hipError_t allow_lds(F* fn, size_t bytes) {
 template <int NP, typename TapT>
 hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
                     hipStream_t s) {
+  // Banded ownership needs enough sub-grid rows to give every wave a band; the LDS-atomic
+  // variant serves narrow sub-grids.  Either can be forced with a flag.
+  bool banded = k->max_width >= 2 * kWaves;
+  if (flags & PG_VARIANT_ATOMIC) banded = false;
+  if (flags & PG_VARIANT_BANDED) banded = true;
+  if (banded) {
+    auto fn = grid_banded_kernel<NP, TapT>;
+    const size_t bytes = k->lds_bytes + kBandScratch;
+    hipError_t e = allow_lds(fn, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(kThreads), bytes, s, p->items.as<Item>(),
+                       p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(), k->planes.as<PlaneInfo>(),
+                       k->os, k->n, grid, flags, static_cast<int>(k->lds_bytes));
+    return hipGetLastError();
+  }
   auto fn = grid_kernel<NP, TapT>;
   hipError_t e = allow_lds(fn, k->lds_bytes);
   if (e != hipSuccess) return e;

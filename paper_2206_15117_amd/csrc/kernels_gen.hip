@@ -109,22 +109,27 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int m, int n, int k, const d
     }
 }
 
-// table[ph_y][ph_x][t_y][t_x][qc] = T[qc][ph_y + t_y os][ph_x + t_x os]
-__global__ void pack_kernel(const double2* __restrict__ t, int support, int os, int nqc, int storage,
+// Table layout per plane: [phase_y][phase_x][chunk][tap_y][tap_x][e], entry (q, c) = chunk * E + e,
+// so that one 16-byte chunk of 64 consecutive taps is 1 KiB of contiguous memory.
+//   table entry = T[qc][ph_y + t_y os][ph_x + t_x os]
+__global__ void pack_kernel(const double2* __restrict__ t, int support, int os, int nqc, int storage, int ce,
                             void* __restrict__ table) {
   const size_t len = static_cast<size_t>(support) * os;
-  const size_t total = len * len * nqc;
+  const size_t ss = static_cast<size_t>(support) * support;
+  const size_t nch = nqc / ce;
+  const size_t total = ss * os * os * nqc;
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < total;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    size_t qc = i % nqc;
-    size_t r = i / nqc;
-    size_t tx = r % support;
-    r /= support;
-    size_t ty = r % support;
-    r /= support;
-    size_t px = r % os;
-    size_t py = r / os;
-    double2 v = t[(qc * len + py + ty * os) * len + px + tx * os];
+    const size_t e = i % ce;
+    size_t r = i / ce;
+    const size_t tap = r % ss;
+    r /= ss;
+    const size_t ch = r % nch;
+    const size_t phase = r / nch;
+    const size_t qc = ch * ce + e;
+    const size_t ty = tap / support, tx = tap % support;
+    const size_t py = phase / os, px = phase % os;
+    const double2 v = t[(qc * len + py + ty * os) * len + px + tx * os];
     if (storage == PG_STORE_F16) {
       // direct float64 -> float16 rounding (no intermediate float32 rounding)
       const _Float16 re = static_cast<_Float16>(v.x), im = static_cast<_Float16>(v.y);
@@ -170,7 +175,8 @@ hipError_t launch_zgemm_nn(int batch, int m, int n, int k, const double2* a, int
 hipError_t launch_pack(const double2* t, int support, int os, int nqc, int storage, void* table, hipStream_t s) {
   size_t total = static_cast<size_t>(support) * os * support * os * nqc;
   int blocks = static_cast<int>(std::min<size_t>((total + 255) / 256, 65535));
-  hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, s, t, support, os, nqc, storage, table);
+  hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, s, t, support, os, nqc, storage,
+                     chunk_entries(storage, nqc), table);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 KIND_GRID, KIND_DEGRID = 0, 1
 STORE_F32, STORE_F16 = 0, 1
 STOKES_IAU, STOKES_PAPER = 0, 1
-ACCUMULATE, FFTSHIFT = 1, 2
+ACCUMULATE, FFTSHIFT, VARIANT_ATOMIC, VARIANT_BANDED = 1, 2, 4, 8
 TAPER_IMAGE, TAPER_PREDICT = 0, 1
 
 
@@ -238,7 +238,8 @@ def _grid_shape(k: Kernels):
     return (k.npol, k.n, k.n)
 
 
-def grid(p: Plan, k: Kernels, vis, out=None, accumulate: bool = False, fftshift: bool = False, stream=None):
+def grid(p: Plan, k: Kernels, vis, out=None, accumulate: bool = False, fftshift: bool = False, stream=None,
+         variant: int = 0):
     import torch
 
     if vis.dtype != torch.complex64 or not vis.is_contiguous() or tuple(vis.shape) != (p.nvis, k.npol):
@@ -247,7 +248,7 @@ def grid(p: Plan, k: Kernels, vis, out=None, accumulate: bool = False, fftshift:
         out = torch.empty(_grid_shape(k), dtype=torch.complex64, device=vis.device)
     elif out.dtype != torch.complex64 or tuple(out.shape) != _grid_shape(k) or not out.is_contiguous():
         raise ValueError("out must be contiguous complex64 [npol, n, n]")
-    flags = (ACCUMULATE if accumulate else 0) | (FFTSHIFT if fftshift else 0)
+    flags = (ACCUMULATE if accumulate else 0) | (FFTSHIFT if fftshift else 0) | int(variant)
     _check(lib().pg_grid(p.handle, k.handle, _ptr(vis), _ptr(out), flags, _stream(stream)))
     return out
 

@@ -71,13 +71,22 @@ class Geometry:
         return int(self.w_planes.shape[0])
 
 
-def default_tiles(support, q, lds_bytes=131072):
-    """Largest tile T (multiple of 4, >= 4) whose (T+S-1)^2 x q complex64 sub-grid fits lds_bytes."""
+def lds_pitch(width: int, support: int) -> int:
+    """Row pitch of a sub-grid in LDS: >= width and congruent to the support modulo 32."""
+    return width + (support - width) % 32
+
+
+def default_tiles(support, q, lds_bytes=163840 - 1152):
+    """Largest tile T per plane whose (T+S-1) x pitch x q complex64 sub-grid fits lds_bytes."""
     out = []
     for s in np.asarray(support):
-        t = 4
-        while (t + 4 + int(s) - 1) ** 2 * q * 8 <= lds_bytes:
-            t += 4
+        s = int(s)
+        t = 1
+        while t < 256:
+            w = t + 1 + s - 1
+            if w * lds_pitch(w, s) * q * 8 > lds_bytes:
+                break
+            t += 1
         out.append(t)
     return np.asarray(out, dtype=np.int32)
 

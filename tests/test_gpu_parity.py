@@ -32,13 +32,17 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
 
 
-def gpu_layout(tables, planes=None):
-    """Oracle tables [Q][C][os][os][S][S] -> the library's [os][os][S][S][Q][C] order, concatenated."""
+def gpu_layout(tables, planes=None, entries=2):
+    """Oracle tables [Q][C][os][os][S][S] -> the library's [os][os][chunk][S][S][e] order, concatenated
+    (Mueller cell q*npol + c = chunk * E + e, E = min(npol^2, entries))."""
     out = []
     for p, t in enumerate(tables):
         if planes is not None and p not in planes:
             continue
-        out.append(np.transpose(t, (2, 3, 4, 5, 0, 1)).ravel())
+        q, c, os_, _, s, _ = t.shape
+        e = min(q * c, entries)
+        a = t.reshape(q * c, os_, os_, s, s).reshape(q * c // e, e, os_, os_, s, s)
+        out.append(np.transpose(a, (2, 3, 0, 4, 5, 1)).ravel())
     return np.concatenate(out)
 
 
@@ -119,7 +123,7 @@ def test_f16_table_is_rounded_oracle_table(c2_case):
     w, _, tg, _, _, _ = c2_case
     k16 = gpu_kernels(w, pg.KIND_GRID, storage=pg.STORE_F16)
     got = host(k16.table()).astype(np.float64)
-    want = gpu_layout(kernels.round_tables(tg, np.float16))
+    want = gpu_layout(kernels.round_tables(tg, np.float16), entries=4)
     assert np.array_equal(got[:, 0], want.real) and np.array_equal(got[:, 1], want.imag)
 
 
@@ -166,10 +170,11 @@ def test_c2_plan_bit_exact_with_drops(c2_case, max_chunk):
 
 # ------------------------------------------------------------------ A3 / A5: grid and degrid
 
-def test_c1_grid_parity(c1_case):
+@pytest.mark.parametrize("variant", [0, pg.VARIANT_BANDED])
+def test_c1_grid_parity(c1_case, variant):
     w, tabs, vis, k = c1_case
     p = pg.plan(k, dev(w.uvw), max_chunk=256)
-    got = host(pg.grid(p, k, dev(vis)))
+    got = host(pg.grid(p, k, dev(vis), variant=variant))
     want = gridding.grid(w.geom, tabs, w.uvw, vis)
     assert rel(got, want) < TOL
 
@@ -184,11 +189,12 @@ def test_c1_degrid_parity(c1_case):
     assert rel(got, want) < TOL
 
 
+@pytest.mark.parametrize("variant", [pg.VARIANT_ATOMIC, pg.VARIANT_BANDED])
 @pytest.mark.parametrize("max_chunk", [64, 2048])
-def test_c2_grid_parity(c2_case, max_chunk):
+def test_c2_grid_parity(c2_case, max_chunk, variant):
     w, vis, tg, _, kg, _ = c2_case
     p = pg.plan(kg, dev(w.uvw), max_chunk=max_chunk)
-    got = host(pg.grid(p, kg, dev(vis)))
+    got = host(pg.grid(p, kg, dev(vis), variant=variant))
     want = gridding.grid(w.geom, tg, w.uvw, vis)
     for q in range(4):
         assert rel(got[q], want[q]) < TOL, q
