@@ -34,10 +34,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nvis", type=int, default=2_300_000)
-    ap.add_argument("--max-chunk", type=int, default=1024)
+    ap.add_argument("--max-chunk", type=int, default=0, help="0: the tuned value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=40000)
+    ap.add_argument("--cpu-sample", type=int, default=450000)
     ap.add_argument("--grid-variant", choices=["auto", "atomic", "banded"], default="auto")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-field section")
     return ap.parse_args()
 
 
@@ -75,8 +76,15 @@ def main():
     torch.cuda.set_device(0)
     pg.use_torch_allocator(True)
     variant = {"auto": 0, "atomic": pg.VARIANT_ATOMIC, "banded": pg.VARIANT_BANDED}[args.grid_variant]
+    from paper_2206_15117_amd import autotune
+
     w = synth.config2(nvis=args.nvis)
-    g = w.geom
+    # launch shape from the autotuner cache (tiles per plane, chunk length, waves per workgroup)
+    g, max_chunk, tuned_variant, gw, dw = autotune.apply(w.geom, 4, pg.STORE_F32)
+    if args.max_chunk:
+        max_chunk = args.max_chunk
+    if variant == 0:
+        variant = {1: pg.VARIANT_ATOMIC, 2: pg.VARIANT_BANDED}.get(tuned_variant, 0)
     jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
     uvw = torch.from_numpy(w.uvw).cuda()
 
@@ -94,7 +102,7 @@ def main():
     ii = np.clip(np.round(w.src_m / g.cell).astype(int) + n // 2, 0, n - 1)
     for s in range(len(jj)):
         model[:, ii[s], jj[s]] += torch.from_numpy(w.src_iquv[s].astype(np.float32)).cuda()
-    p0 = pg.plan(kd, uvw, max_chunk=args.max_chunk)
+    p0 = pg.plan(kd, uvw, max_chunk=max_chunk).set_launch(0, gw, dw)
     vis = pg.predict(p0, kd, model)
     del p0
 
@@ -108,7 +116,7 @@ def main():
         e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         if record:
             e[0].record()
-        p = pg.plan(kg, uvw, max_chunk=args.max_chunk)
+        p = pg.plan(kg, uvw, max_chunk=max_chunk).set_launch(0, gw, dw)
         if record:
             e[1].record()
         pg.grid(p, kg, vis, out=grid_buf, fftshift=True, variant=variant)
@@ -160,7 +168,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "full-pol A+W 2048x2048x4, 32 w-planes, support 16-48, os 8, "
                                "Gaussian 1deg beam + 1% leakage, 36 ant / 630 baselines, 2.3M rows",
-                   "nvis": w.nvis, "n_kept": p.n_kept, "n_items": p.n_items, "max_chunk": args.max_chunk,
+                   "nvis": w.nvis, "n_kept": p.n_kept, "n_items": p.n_items, "max_chunk": max_chunk,
+                   "grid_waves": gw, "degrid_waves": dw, "tiles": [int(t) for t in g.tile],
                    "mean_support_sq": s2_sum / max(p.n_kept, 1)},
         "breakdown_ms": ms, "make_kernels_s": t_kernels,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
@@ -168,9 +177,108 @@ def main():
                      "hbm_frac_alg": bytes_alg / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "source_hash": src,
     }
+    if not args.no_batched:
+        del grid_buf, fft_buf, img, vis_out
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(max(2, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(steps, warmup):
+    """16 channels with uneven row counts, each on its own 4096^2 x 4 grid with float16 tables:
+    grid (one persistent launch over all fields) -> FFT -> taper -> taper -> inverse FFT ->
+    degrid (one persistent launch), the whole step captured in one HIP graph and replayed."""
+    import torch
+
+    import synth
+    from paper_2206_15117_amd import polgrid as pg
+
+    fields = synth.config3()
+    nf = len(fields)
+    n = fields[0].geom.n
+    t0 = time.perf_counter()
+    ks, ps, vis, outs = [], [], [], []
+    rng = np.random.default_rng(33)
+    from paper_2206_15117_amd import autotune
+
+    for w in fields:
+        g, chunk, _, gw, dw = autotune.apply(w.geom, 4, pg.STORE_F16)
+        jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
+        kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=0.2, storage=pg.STORE_F16)
+        kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones, storage=pg.STORE_F16)
+        uvw = torch.from_numpy(w.uvw).cuda()
+        ks.append((kg, kd))
+        ps.append((pg.plan(kg, uvw, max_chunk=chunk).set_launch(0, gw, dw),
+                   pg.plan(kd, uvw, max_chunk=chunk).set_launch(0, gw, dw)))
+        vis.append(torch.from_numpy(synth.random_vis(w.nvis, 4, rng)).cuda())
+        outs.append(torch.empty((w.nvis, 4), dtype=torch.complex64, device="cuda"))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    grids = torch.empty((nf, 4, n, n), dtype=torch.complex64, device="cuda")
+    imgs = torch.empty((nf, 4, n, n), dtype=torch.float32, device="cuda")
+    model = torch.empty((nf, 4, n, n), dtype=torch.complex64, device="cuda")
+    bg = pg.batch([(ps[f][0], ks[f][0], vis[f], grids[f]) for f in range(nf)])
+    gmodel = torch.empty_like(grids)
+    spec = torch.empty_like(grids)
+    bd = pg.batch([(ps[f][1], ks[f][1], outs[f], gmodel[f]) for f in range(nf)])
+
+    def step():
+        bg.grid(fftshift=True)
+        torch.fft.fft2(grids, out=spec)
+        for f in range(nf):
+            pg.taper(ks[f][0], spec[f], imgs[f], pg.TAPER_IMAGE, float(ps[f][0].n_kept))
+            pg.taper(ks[f][1], imgs[f], model[f], pg.TAPER_PREDICT)
+        torch.fft.ifft2(model, norm="forward", out=gmodel)
+        bd.degrid(fftshift=True)
+
+    # eager breakdown of the two persistent launches
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    step()
+    ev[0].record()
+    bg.grid(fftshift=True)
+    ev[1].record()
+    ev[2].record()
+    bd.degrid(fftshift=True)
+    ev[3].record()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    rows = sum(w.nvis for w in fields)
+    # image error of float16 tables against float32 tables on the smallest field
+    f = int(np.argmin([w.nvis for w in fields]))
+    w = fields[f]
+    jones = synth.jones_on_lattice(w.beam, w.geom.mk, w.geom.fov)
+    k32 = pg.make_kernels(ks[f][0].geom, 4, pg.KIND_GRID, jones=jones, eps_null=0.2)
+    p32 = pg.plan(k32, torch.from_numpy(w.uvw).cuda(), max_chunk=256)
+    i32 = pg.image(p32, k32, vis[f], float(p32.n_kept))
+    i16 = imgs[f]
+    aa = torch.from_numpy(np.outer(k32.aa_pixels, k32.aa_pixels)).cuda()
+    ok = aa >= 1e-2
+    err = float((i16[:, ok] - i32[:, ok]).norm() / i32[:, ok].norm())
+    return {"workload": f"{nf} channels 700-1800 MHz, rows log-uniform 0.1M-4M (seeded), each its own "
+                        f"{n}x{n}x4 grid, float16 tables, 32 w-planes, supports 16-48, os 8",
+            "rows": rows, "value": rows / (ms * 1e-3), "unit": "vis/s", "ms_per_step": ms,
+            "hip_graph": True, "work_items": bg.work_items + bd.work_items,
+            "grid_ms": ev[0].elapsed_time(ev[1]), "degrid_ms": ev[2].elapsed_time(ev[3]),
+            "setup_s": t_setup, "image_rel_err_f16_vs_f32": err}
 
 
 def cpu_baseline(w, nsample):

@@ -88,7 +88,7 @@ typedef struct pg_geometry {
   const int32_t* support;  /* host [nplanes], taps per axis, 1 .. 64 */
   const int32_t* tile;     /* host [nplanes], uv tile side used to bin visibilities, >= 1; the
                               sub-grid (tile + support - 1) rows x pitch x npol x 8 B must fit
-                              162688 B of LDS, pitch = the width rounded up to == support mod 32 */
+                              162560 B of LDS, pitch = the width rounded up to == support mod 32 */
   int32_t aa_support;      /* support of the prolate spheroidal anti-aliasing function (7) */
   int32_t mk;              /* samples per side of the image lattice kernels are built on (even) */
 } pg_geometry;
@@ -146,7 +146,7 @@ void pg_set_allocator(void* (*alloc_fn)(size_t, void*, void*),
  * the mk x mk lattice, restricted to offsets |d| < S_p os / 2.  Host float64
  * Mueller algebra, device float64 transforms, stored in spec->storage.
  * Synchronises `stream`.  Errors: PG_EINVAL (bad spec), PG_EUNSUPPORTED (sub-grid
- * of some plane larger than the 162688-byte LDS budget), PG_ENOMEM, PG_EHIP. */
+ * of some plane larger than the 162560-byte LDS budget), PG_ENOMEM, PG_EHIP. */
 int pg_make_kernels(const pg_kernel_spec* spec, void* stream, pg_kernels** out);
 int pg_kernels_info(const pg_kernels* k, pg_kernels_desc* out);
 /* Copy the whole table (plane_offset[nplanes] entries of 8 bytes (F32) or 4 bytes (F16)) into
@@ -167,6 +167,12 @@ int pg_plan_info(const pg_plan* p, pg_plan_desc* out);
 int pg_plan_copy(const pg_plan* p, int32_t* perm, int32_t* fine, int32_t* items, void* stream);
 void pg_plan_destroy(pg_plan* p);
 
+/* Launch tuning of the kernels that run over this plan (results are unchanged up to float32
+ * summation order): grid_variant 0 = choose by sub-grid width, 1 = LDS-atomic accumulation,
+ * 2 = row-band ownership; grid_waves and degrid_waves = waves per workgroup, 4, 8 or 16.
+ * Set before the plan is shared between threads.  Errors: PG_EINVAL. */
+int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves);
+
 /* Gridding (Sec. 3.2, Sec. 4):
  *   G_q(X,Y) (+)= sum_k sum_c T_{p_k,q,c}(X os - fine_x,k, Y os - fine_y,k) V_{k,c}.
  * vis: complex64 [nvis][npol] (the plan's nvis); grid: complex64 [npol][n][n].
@@ -179,6 +185,73 @@ int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, 
  * grid: complex64 [npol][n][n]; vis_out: complex64 [nvis][npol].  Enqueue only. */
 int pg_degrid(const pg_plan* p, const pg_kernels* k, const void* grid, void* vis_out, int32_t flags,
               void* stream);
+
+/* Overwrite one Mueller cell (q, c) of one plane of a kernel set with caller data: src is device
+ * float [os][os][S][S][2] (phase_y, phase_x, tap_y, tap_x, re/im), converted to the table's
+ * storage.  Used to run the gridder on generated (e.g. learned) kernels; call before the kernel
+ * set is shared.  Enqueue only.  Errors: PG_EINVAL. */
+int pg_kernels_write_cell(pg_kernels* k, int32_t plane, int32_t q, int32_t c, const float* src, void* stream);
+
+/* ------------------------------------------------------------------ kernel surrogate network
+ * A multilayer perceptron that emits one oversampled kernel cell from a feature vector: hidden
+ * layers of `width` SiLU units, a linear output layer of n_out values.  Weights are float32
+ * masters with bfloat16 copies; every product runs on the matrix cores with bfloat16 operands
+ * and float32 accumulation; training minimises (1/B) sum_b |y_b - t_b|^2 / |t_b|^2 with Adam
+ * (beta 0.9, 0.999, eps 1e-8).  Weights start U(-a, a), a = sqrt(6 / fan_in) (sqrt(3 / fan_in)
+ * for the output layer), from a counter-based generator (splitmix64 of seed + index).
+ * Not in the paper: a learned replacement for on-the-fly kernel generation. */
+typedef struct pg_mlp pg_mlp;
+#define PG_MLP_W 0      /* float [d_in][d_out] master weights of a layer */
+#define PG_MLP_W_BF16 1 /* bfloat16 copy */
+#define PG_MLP_B 2      /* float [d_out] bias */
+#define PG_MLP_GW 3     /* float [d_in][d_out] weight gradient of the last train step */
+#define PG_MLP_GB 4     /* float [d_out] bias gradient */
+#define PG_MLP_ACT 5    /* bfloat16 [batch][d_in] input activation of the layer (layer 0: features) */
+#define PG_MLP_PRE 6    /* float [batch][d_out] pre-activation (output layer: the network output) */
+#define PG_MLP_GY 7     /* float [batch][n_out] loss gradient at the output (last train step) */
+#define PG_MLP_GY_BF16 8 /* its bfloat16 copy, the operand of the output layer's gradient products */
+#define PG_MLP_GZ 9     /* float [batch][d_1] gradient at the first layer's pre-activation */
+#define PG_MLP_GZ_BF16 10 /* its bfloat16 copy */
+
+int pg_mlp_create(int32_t n_in, int32_t width, int32_t hidden_layers, int64_t n_out, int32_t max_batch,
+                  uint64_t seed, void* stream, pg_mlp** out);
+/* x: device float [batch][n_in]; y: device float [batch][n_out] or NULL.  Enqueue only. */
+int pg_mlp_forward(pg_mlp* m, const float* x, int32_t batch, float* y, void* stream);
+/* Forward, loss, backward and (if update) one Adam step; loss_out: device float or NULL. */
+int pg_mlp_train_step(pg_mlp* m, const float* x, const float* target, int32_t batch, float lr, int32_t update,
+                      float* loss_out, void* stream);
+/* Copy a parameter, gradient or activation of `layer` (0 = first) into device memory. */
+int pg_mlp_copy(const pg_mlp* m, int32_t what, int32_t layer, void* dst, void* stream);
+/* Set a layer's float weights [d_in][d_out] and bias [d_out] from device memory. */
+int pg_mlp_load(pg_mlp* m, int32_t layer, const float* w, const float* b, void* stream);
+void pg_mlp_destroy(pg_mlp* m);
+
+/* ------------------------------------------------------------------ batched launch
+ * Many fields (channels or mosaic pointings, each with its own plan, kernels, visibilities and
+ * grid; uneven visibility counts) gridded or degridded by ONE persistent launch: workgroups pull
+ * (field, work item) pairs from a device queue ordered largest item first, so uneven fields
+ * balance across the GPU (multi-field mosaics and channel-dependent beams, Sec. 2.2, Sec. 3.2).
+ * All fields share npol and table storage; geometries may differ.  The launch shape (waves per
+ * workgroup) is taken from the first field's plan (pg_plan_set_launch). */
+typedef struct pg_field {
+  const pg_plan* plan;
+  const pg_kernels* kernels;
+  void* vis;   /* complex64 [nvis][npol] device: input of pg_batch_grid, output of pg_batch_degrid */
+  void* grid;  /* complex64 [npol][n][n] device: output of pg_batch_grid, input of pg_batch_degrid */
+} pg_field;
+typedef struct pg_batch pg_batch;
+
+/* Builds the device field table and the ordered work queue; the plans, kernels and buffers must
+ * outlive the batch.  Synchronises `stream`.  Errors: PG_EINVAL (NULLs, npol or storage mismatch,
+ * plan/kernel geometry mismatch), PG_ENOMEM, PG_EHIP. */
+int pg_batch_create(const pg_field* fields, int32_t nfields, void* stream, pg_batch** out);
+/* Enqueue: zero every grid (unless PG_ACCUMULATE), reset the queue, one persistent grid launch.
+ * Allocates nothing and calls only kernel launches, so it may be captured in a HIP graph. */
+int pg_batch_grid(const pg_batch* b, int32_t flags, void* stream);
+/* Enqueue: zero dropped visibilities, reset the queue, one persistent degrid launch.  Capturable. */
+int pg_batch_degrid(const pg_batch* b, int32_t flags, void* stream);
+int64_t pg_batch_work_items(const pg_batch* b);
+void pg_batch_destroy(pg_batch* b);
 
 /* Image-domain taper correction around the FFT (Sec. 2.2, Sec. 3.2).
  * PG_TAPER_IMAGE:   in complex64 [npol][n][n] = FFT of a PG_FFTSHIFT grid;

@@ -1,0 +1,193 @@
+"""Autotuner for the gridder's launch shape.
+
+Searches, per geometry class (npol, storage, os, per-plane supports):
+  * workgroups per CU (1-4): sets each plane's tile T to the largest sub-grid that fits
+    1/k of the LDS, so every item of a launch has the same LDS footprint;
+  * waves per workgroup for grid and degrid (4, 8, 16);
+  * the grid variant (row bands or LDS atomics) and the chunk length of work items.
+Each candidate is timed with HIP events on a representative workload; the best choice is
+cached in tuning.json beside this file and read back by `tuned_config`.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning.json")
+LDS_CU = 163840            # LDS per CU
+LDS_SCRATCH = 1280         # per-workgroup gridder scratch (row loads, band bounds, queue slot)
+
+
+def lds_pitch(width: int, support: int) -> int:
+    return width + (support - width) % 32
+
+
+def tiles_for(support, npol: int, wgs_per_cu: int, min_tile: int = 1):
+    """Largest tile per plane whose (T+S-1) x pitch x npol x 8 B sub-grid, plus the gridder
+    scratch, lets wgs_per_cu workgroups share one CU's LDS."""
+    budget = LDS_CU // wgs_per_cu - LDS_SCRATCH
+    out = []
+    for s in np.asarray(support):
+        s = int(s)
+        t = min_tile
+        while t < 512:
+            w = t + 1 + s - 1
+            if w * lds_pitch(w, s) * npol * 8 > budget:
+                break
+            t += 1
+        w = t + s - 1
+        if w * lds_pitch(w, s) * npol * 8 > budget:
+            return None
+        out.append(t)
+    return np.asarray(out, dtype=np.int32)
+
+
+def key_of(npol, storage, os_, support) -> str:
+    return f"np{npol}-st{storage}-os{os_}-S" + ",".join(str(int(s)) for s in support)
+
+
+def tuned_config(npol, storage, os_, support):
+    """Cached best launch shape for this geometry class; else the entry of the same npol and storage
+    (its launch shape, with tiles recomputed for these supports); else None."""
+    if not os.path.exists(CACHE):
+        return None
+    with open(CACHE) as fh:
+        data = json.load(fh)
+    hit = data.get(key_of(npol, storage, os_, support))
+    if hit is not None:
+        return hit
+    prefix = f"np{npol}-st{storage}-"
+    for k, v in sorted(data.items()):
+        if k.startswith(prefix):
+            out = json.loads(json.dumps(v))
+            for d in ("grid", "degrid"):
+                t = tiles_for(support, npol, out[d]["wgs_per_cu"])
+                if t is None:
+                    return None
+                out[d]["tiles"] = t.tolist()
+            return out
+    return None
+
+
+def apply(geom, npol, storage):
+    """(geometry with tuned tiles, max_chunk, grid variant, grid waves, degrid waves) for this
+    geometry, using the grid direction's tiles for both directions when they differ."""
+    import copy
+
+    cfg = tuned_config(npol, storage, geom.os, geom.support)
+    g = copy.copy(geom)
+    if cfg is None:
+        return g, 1024, 0, 16, 16
+    g.tile = np.asarray(cfg["grid"]["tiles"], dtype=np.int32)
+    same = cfg["grid"]["wgs_per_cu"] == cfg["degrid"]["wgs_per_cu"]
+    return (g, int(cfg["grid"]["max_chunk"]), int(cfg["grid"].get("variant", 2)), int(cfg["grid"]["waves"]),
+            int(cfg["degrid"]["waves"]) if same else 16)
+
+
+def _time(fn, reps):
+    import torch
+
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2, 3, 4),
+         waves=(4, 8, 16), chunks=(256, 1024), verbose=True):
+    """Time every candidate; returns (best dict, list of all results)."""
+    import copy
+
+    import torch
+
+    from . import polgrid as pg
+
+    grid = torch.empty((npol, geom.n, geom.n), dtype=torch.complex64, device="cuda")
+    out = torch.empty_like(vis)
+    results = []
+    for k in wgs:
+        tiles = tiles_for(geom.support, npol, k)
+        if tiles is None:
+            continue
+        g = copy.copy(geom)
+        g.tile = tiles
+        kg = pg.make_kernels(g, npol, pg.KIND_GRID, jones=jones, eps_null=eps_null, storage=storage)
+        kd = pg.make_kernels(g, npol, pg.KIND_DEGRID, jones=jones, storage=storage)
+        for chunk in chunks:
+            p = pg.plan(kg, uvw, max_chunk=chunk)
+            for nw in waves:
+                for variant in (2, 1):
+                    if variant == 1 and nw != 16:
+                        continue
+                    p.set_launch(variant, nw, nw)
+                    tg = _time(lambda: pg.grid(p, kg, vis, out=grid, fftshift=True), reps)
+                    td = _time(lambda: pg.degrid(p, kd, grid, out=out, fftshift=True), reps)
+                    r = dict(wgs_per_cu=k, max_chunk=chunk, waves=nw, variant=variant,
+                             grid_ms=tg, degrid_ms=td, tiles=tiles.tolist())
+                    results.append(r)
+                    if verbose:
+                        print(json.dumps(r), flush=True)
+    bg = min(results, key=lambda r: r["grid_ms"])
+    bd = min(results, key=lambda r: r["degrid_ms"])
+    best = dict(grid=dict(wgs_per_cu=bg["wgs_per_cu"], max_chunk=bg["max_chunk"], waves=bg["waves"],
+                          variant=bg["variant"], ms=bg["grid_ms"], tiles=bg["tiles"]),
+                degrid=dict(wgs_per_cu=bd["wgs_per_cu"], max_chunk=bd["max_chunk"], waves=bd["waves"],
+                            ms=bd["degrid_ms"], tiles=bd["tiles"]))
+    return best, results
+
+
+def save(npol, storage, os_, support, best, results=None, note=""):
+    data = {}
+    if os.path.exists(CACHE):
+        with open(CACHE) as fh:
+            data = json.load(fh)
+    entry = dict(best)
+    entry["note"] = note
+    entry["when"] = time.strftime("%Y-%m-%d")
+    data[key_of(npol, storage, os_, support)] = entry
+    with open(CACHE, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+
+
+def main():
+    import argparse
+    import sys
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(HERE))
+    import synth
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c2", choices=["c2"])
+    ap.add_argument("--storage", type=int, default=0)
+    ap.add_argument("--quick", action="store_true", help="fewer candidates")
+    ap.add_argument("--save", action="store_true")
+    args = ap.parse_args()
+    from . import polgrid as pg
+
+    torch.cuda.set_device(0)
+    pg.use_torch_allocator(True)
+    w = synth.config2()
+    g = w.geom
+    jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
+    uvw = torch.from_numpy(w.uvw).cuda()
+    vis = torch.from_numpy(synth.random_vis(w.nvis, 4, np.random.default_rng(3))).cuda()
+    kw = dict(wgs=(1, 2, 4), waves=(4, 16), chunks=(256,)) if args.quick else {}
+    best, results = tune(g, 4, jones, uvw, vis, w.eps_null, storage=args.storage, **kw)
+    print("BEST", json.dumps(best), flush=True)
+    if args.save:
+        save(4, args.storage, g.os, g.support, best, results, note=f"{w.name}, {w.nvis} rows")
+        print("CACHE", json.dumps({key_of(4, args.storage, g.os, g.support): best}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

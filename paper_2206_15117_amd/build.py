@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpolgrid.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "pswf.cpp", "mueller.cpp", "kernels_gen.hip", "plan.hip", "grid.hip"]
+SOURCES = ["api.cpp", "pswf.cpp", "mueller.cpp", "kernels_gen.hip", "plan.hip", "grid.hip", "mlp.hip",
+           "mlp_api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]

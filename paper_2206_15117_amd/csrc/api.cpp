@@ -17,7 +17,7 @@ namespace {
 thread_local std::string g_error;
 std::mutex g_alloc_mu;
 Allocator g_alloc;
-constexpr size_t kLdsBudget = 160 * 1024 - 1152;  // sub-grid share of the 160 KiB; the rest is gridder scratch
+constexpr size_t kLdsBudget = 160 * 1024 - 1280;  // sub-grid share of the 160 KiB; the rest is gridder scratch
 
 int fail(int code, const std::string& msg) {
   g_error = msg;
@@ -52,7 +52,7 @@ int check_geometry(const pg_geometry& g, int npol) {
     const int w = g.tile[p] + g.support[p] - 1;
     if (static_cast<size_t>(w) * lds_pitch(w, g.support[p]) * npol * 8 > kLdsBudget)
       return fail(PG_EUNSUPPORTED, "plane " + std::to_string(p) +
-                                       ": sub-grid (tile + support - 1) rows x padded pitch x npol x 8 B exceeds 158.875 KiB of LDS");
+                                       ": sub-grid (tile + support - 1) rows x padded pitch x npol x 8 B exceeds 162560 B of LDS");
   }
   if (g.aa_support < 1 || g.aa_support > 64) return fail(PG_EINVAL, "aa_support must be in [1, 64]");
   if (g.mk < 2 || g.mk > 4096 || (g.mk & 1)) return fail(PG_EINVAL, "mk must be even and in [2, 4096]");
@@ -336,6 +336,18 @@ int pg_plan_copy(const pg_plan* p, int32_t* perm, int32_t* fine, int32_t* items,
 
 void pg_plan_destroy(pg_plan* p) { delete p; }
 
+int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves) {
+  g_error.clear();
+  if (!p) return fail(PG_EINVAL, "plan must be non-NULL");
+  if (grid_variant < 0 || grid_variant > 2) return fail(PG_EINVAL, "grid_variant must be 0, 1 or 2");
+  auto ok = [](int w) { return w == 4 || w == 8 || w == 16; };
+  if (!ok(grid_waves) || !ok(degrid_waves)) return fail(PG_EINVAL, "waves per workgroup must be 4, 8 or 16");
+  p->grid_variant = grid_variant;
+  p->grid_waves = grid_waves;
+  p->degrid_waves = degrid_waves;
+  return PG_OK;
+}
+
 int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, int32_t flags, void* stream) {
   g_error.clear();
   int rc = check_run(p, k, vis, grid, flags, PG_ACCUMULATE | PG_FFTSHIFT | PG_VARIANT_ATOMIC | PG_VARIANT_BANDED);
@@ -355,6 +367,98 @@ int pg_degrid(const pg_plan* p, const pg_kernels* k, const void* grid, void* vis
                        static_cast<hipStream_t>(stream)), "degrid");
   return PG_OK;
 }
+
+int pg_batch_create(const pg_field* fields, int32_t nfields, void* stream, pg_batch** out) {
+  g_error.clear();
+  try {
+    if (!fields || !out || nfields < 1 || nfields > 65536)
+      return fail(PG_EINVAL, "fields and out must be non-NULL and nfields in [1, 65536]");
+    *out = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto* b = new (std::nothrow) pg_batch();
+    if (!b) return fail(PG_ENOMEM, "host allocation failed");
+    std::unique_ptr<pg_batch> guard(b);
+    b->nfields = nfields;
+    std::vector<FieldArgs> fa(nfields);
+    struct Cost {
+      int64_t cost;
+      int32_t field, item;
+    };
+    std::vector<Cost> costs;
+    for (int f = 0; f < nfields; ++f) {
+      const pg_field& fd = fields[f];
+      if (!fd.plan || !fd.kernels || !fd.grid) return fail(PG_EINVAL, "field " + std::to_string(f) + ": NULL plan, kernels or grid");
+      if (!fd.vis && fd.plan->nvis > 0) return fail(PG_EINVAL, "field " + std::to_string(f) + ": NULL visibilities");
+      if (!same_geometry(fd.plan, fd.kernels)) return fail(PG_EINVAL, "field " + std::to_string(f) + ": plan and kernels differ in geometry");
+      if (f == 0) {
+        b->npol = fd.kernels->npol;
+        b->storage = fd.kernels->storage;
+        b->grid_waves = fd.plan->grid_waves;
+        b->degrid_waves = fd.plan->degrid_waves;
+      } else if (fd.kernels->npol != b->npol || fd.kernels->storage != b->storage) {
+        return fail(PG_EINVAL, "all fields of a batch must share npol and table storage");
+      }
+      b->plans.push_back(fd.plan);
+      b->kernels.push_back(fd.kernels);
+      b->vis.push_back(fd.vis);
+      b->grids.push_back(fd.grid);
+      b->lds_bytes = std::max(b->lds_bytes, fd.kernels->lds_bytes);
+      fa[f] = FieldArgs{fd.plan->items.as<Item>(), fd.plan->fine.as<int2>(), fd.plan->perm.as<int32_t>(),
+                        static_cast<float2*>(fd.vis), fd.kernels->table.p, fd.kernels->planes.as<PlaneInfo>(),
+                        static_cast<float2*>(fd.grid), fd.kernels->os, fd.kernels->n};
+      std::vector<Item> items(fd.plan->n_items);
+      if (fd.plan->n_items) {
+        PG_HIP(hipMemcpyAsync(items.data(), fd.plan->items.p, sizeof(Item) * items.size(), hipMemcpyDeviceToHost, s),
+               "read items");
+        PG_HIP(hipStreamSynchronize(s), "batch sync");
+      }
+      for (int64_t i = 0; i < fd.plan->n_items; ++i) {
+        const int S = fd.kernels->support[items[i].plane];
+        const int W = fd.kernels->tile[items[i].plane] + S - 1;
+        costs.push_back({static_cast<int64_t>(items[i].end - items[i].start) * S * S + static_cast<int64_t>(W) * W,
+                         f, static_cast<int32_t>(i)});
+      }
+    }
+    std::stable_sort(costs.begin(), costs.end(), [](const Cost& a, const Cost& c) { return a.cost > c.cost; });
+    b->n_work = static_cast<int64_t>(costs.size());
+    std::vector<int2> work(costs.size());
+    for (size_t i = 0; i < costs.size(); ++i) work[i] = make_int2(costs[i].field, costs[i].item);
+    int dev = 0;
+    PG_HIP(hipGetDevice(&dev), "get device");
+    PG_HIP(hipDeviceGetAttribute(&b->n_cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    if (!b->fields.alloc(sizeof(FieldArgs) * nfields, s) || !b->work.alloc(sizeof(int2) * std::max<size_t>(work.size(), 1), s) ||
+        !b->counter.alloc(8, s))
+      return fail(PG_ENOMEM, "device allocation failed in batch_create");
+    PG_HIP(hipMemcpyAsync(b->fields.p, fa.data(), sizeof(FieldArgs) * nfields, hipMemcpyHostToDevice, s), "upload fields");
+    if (!work.empty())
+      PG_HIP(hipMemcpyAsync(b->work.p, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, s), "upload work");
+    PG_HIP(hipStreamSynchronize(s), "batch sync");
+    *out = guard.release();
+    return PG_OK;
+  } catch (...) {
+    return fail(PG_ENOMEM, "exception in batch_create");
+  }
+}
+
+int pg_batch_grid(const pg_batch* b, int32_t flags, void* stream) {
+  g_error.clear();
+  if (!b) return fail(PG_EINVAL, "batch must be non-NULL");
+  if (flags & ~(PG_ACCUMULATE | PG_FFTSHIFT)) return fail(PG_EINVAL, "unknown flag bits");
+  PG_HIP(launch_batch_grid(b, flags, static_cast<hipStream_t>(stream)), "batch grid");
+  return PG_OK;
+}
+
+int pg_batch_degrid(const pg_batch* b, int32_t flags, void* stream) {
+  g_error.clear();
+  if (!b) return fail(PG_EINVAL, "batch must be non-NULL");
+  if (flags & ~PG_FFTSHIFT) return fail(PG_EINVAL, "unknown flag bits");
+  PG_HIP(launch_batch_degrid(b, flags, static_cast<hipStream_t>(stream)), "batch degrid");
+  return PG_OK;
+}
+
+int64_t pg_batch_work_items(const pg_batch* b) { return b ? b->n_work : -1; }
+
+void pg_batch_destroy(pg_batch* b) { delete b; }
 
 int pg_taper(const pg_kernels* k, const void* in, void* out, int32_t direction, double weight_sum, void* stream) {
   g_error.clear();

@@ -40,6 +40,18 @@ inline int chunk_entries(int storage, int nqc) {
   return nqc < e ? nqc : e;
 }
 
+// One field (channel or mosaic pointing) of a batched launch, as the device sees it.
+struct FieldArgs {
+  const Item* items;
+  const int2* fine;
+  const int32_t* perm;
+  float2* vis;        // grid: input, degrid: output
+  const void* table;  // float2 or __half2 entries
+  const PlaneInfo* planes;
+  float2* grid;       // grid: output, degrid: input
+  int32_t os, n;
+};
+
 void set_error(const std::string& msg);
 
 // Registered device allocator (hipMalloc/hipFree when both hooks are NULL).
@@ -59,6 +71,22 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), s(o.s), a(o.a) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p;
+      bytes = o.bytes;
+      s = o.s;
+      a = o.a;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevBuf() { reset(); }
   bool alloc(size_t b, hipStream_t st) {
     reset();
@@ -109,11 +137,27 @@ struct pg_plan {
   int64_t nvis = 0, n_kept = 0, n_dropped = 0, n_items = 0;
   int32_t max_chunk = 0;
   int32_t n = 0, os = 0;                // geometry the plan was binned for
+  int32_t grid_variant = 0;             // 0 auto, 1 LDS atomics, 2 row bands
+  int32_t grid_waves = 16, degrid_waves = 16;  // waves per workgroup
   std::vector<int32_t> support, tile;
   pg::DevBuf perm;    // int32 [nvis]
   pg::DevBuf fine;    // int2 [n_kept]
   pg::DevBuf items;   // Item [n_items]
   pg::DevBuf counter; // int32 work queue head for the persistent launch
+};
+
+struct pg_batch {
+  int32_t nfields = 0, npol = 1, storage = 0;
+  int64_t n_work = 0;
+  size_t lds_bytes = 0;          // largest sub-grid over the fields
+  int32_t grid_waves = 16, degrid_waves = 16;
+  int32_t n_cus = 256;
+  std::vector<const pg_plan*> plans;
+  std::vector<const pg_kernels*> kernels;
+  std::vector<void*> vis, grids;
+  pg::DevBuf fields;   // FieldArgs [nfields]
+  pg::DevBuf work;     // int2 (field, item) [n_work], largest item first
+  pg::DevBuf counter;  // queue head (8 bytes, zeroed before each launch)
 };
 
 // ---- launchers implemented in the .hip files (all enqueue on `s`)
@@ -154,6 +198,8 @@ hipError_t launch_degrid(const pg_plan* p, const pg_kernels* k, const float2* gr
                          hipStream_t s);
 hipError_t launch_taper(const pg_kernels* k, const void* in, void* out, int direction, double weight_sum,
                         hipStream_t s);
+hipError_t launch_batch_grid(const pg_batch* b, int flags, hipStream_t s);
+hipError_t launch_batch_degrid(const pg_batch* b, int flags, hipStream_t s);
 
 // Host numerics (pswf.cpp, mueller.cpp)
 std::vector<double> pswf0(double c, const std::vector<double>& x);

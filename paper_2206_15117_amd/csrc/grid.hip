@@ -147,31 +147,27 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(const Item* __restrict__
   }
 }
 
-// Banded variant: the sub-grid rows are split into kWaves contiguous bands of equal load (rows
+// Banded variant: the sub-grid rows are split into NW contiguous bands of equal load (rows
 // weighted by how many footprints of the item cover them); wave w owns band w and walks every
 // visibility of the item, taking only the footprint rows inside its band.  Bands are disjoint, so
 // the sub-grid (complex [q][W][P] in LDS) is updated with plain read-modify-write, no LDS atomics.
-template <int NP, typename TapT>
-__global__ __launch_bounds__(kThreads) void grid_banded_kernel(const Item* __restrict__ items,
-                                                               const int2* __restrict__ fine,
-                                                               const int32_t* __restrict__ perm,
-                                                               const float2* __restrict__ vis,
-                                                               const TapT* __restrict__ table,
-                                                               const PlaneInfo* __restrict__ planes, int os, int n,
-                                                               float2* __restrict__ grid, int flags, int sub_bytes) {
-  extern __shared__ float lds_f[];
+template <int NP, typename TapT, int NW>
+__device__ __forceinline__ void grid_item_banded(const Item it, const int2* __restrict__ fine,
+                                                 const int32_t* __restrict__ perm, const float2* __restrict__ vis,
+                                                 const TapT* __restrict__ table, const PlaneInfo* __restrict__ planes,
+                                                 int os, int n, float2* __restrict__ grid, int flags, int sub_bytes,
+                                                 float* lds_f) {
   float2* lds = reinterpret_cast<float2*>(lds_f);
   int* rowload = reinterpret_cast<int*>(reinterpret_cast<char*>(lds_f) + sub_bytes);  // [W + 1]
-  int* band = rowload + 256;                                                             // [kWaves + 1]
-  const Item it = items[blockIdx.x];
+  int* band = rowload + 256;                                                             // [NW + 1]
   const PlaneInfo pl = planes[it.plane];
   const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
   const float inv_s = 1.0f / static_cast<float>(S);
-  for (int i = threadIdx.x; i < NP * WP; i += kThreads) lds[i] = make_float2(0.0f, 0.0f);
-  for (int i = threadIdx.x; i <= W; i += kThreads) rowload[i] = 0;
+  for (int i = threadIdx.x; i < NP * WP; i += (NW * 64)) lds[i] = make_float2(0.0f, 0.0f);
+  for (int i = threadIdx.x; i <= W; i += (NW * 64)) rowload[i] = 0;
   __syncthreads();
   // coverage count of every sub-grid row (difference array, then a prefix sum in one wave)
-  for (int i = it.start + static_cast<int>(threadIdx.x); i < it.end; i += kThreads) {
+  for (int i = it.start + static_cast<int>(threadIdx.x); i < it.end; i += (NW * 64)) {
     const int ly = ceil_div_i(fine[i].y - half + 1, os) - it.oy;
     atomicAdd(&rowload[ly], 1);
     atomicAdd(&rowload[ly + S], -1);
@@ -205,14 +201,14 @@ __global__ __launch_bounds__(kThreads) void grid_banded_kernel(const Item* __res
       if (r0 + lane < W) rowload[r0 + lane] = c;
     }
     __builtin_amdgcn_wave_barrier();
-    // band w starts at the first row whose cumulative load reaches w / kWaves of the total
-    if (lane <= kWaves) {
+    // band w starts at the first row whose cumulative load reaches w / NW of the total
+    if (lane <= NW) {
       const long long total = rowload[W - 1];
       int r = 0;
-      if (lane == kWaves) {
+      if (lane == NW) {
         r = W;
       } else if (lane > 0) {
-        const long long thr = (total * lane + kWaves - 1) / kWaves;
+        const long long thr = (total * lane + NW - 1) / NW;
         while (r < W && rowload[r] < thr) ++r;
         ++r;
         if (r > W) r = W;
@@ -222,21 +218,36 @@ __global__ __launch_bounds__(kThreads) void grid_banded_kernel(const Item* __res
   }
   __syncthreads();
   const int r0 = band[wave], r1 = band[wave + 1];
-  int2 f = uniform(it.start < it.end ? fine[it.start] : make_int2(0, 0));
-  for (int i = it.start; i < it.end && r0 < r1; ++i) {
-    const int2 fn = uniform((i + 1 < it.end) ? fine[i + 1] : f);  // next metadata in flight early
-    const int y0 = ceil_div_i(f.y - half + 1, os);
-    const int ly = y0 - it.oy;
-    const int a = max(ly, r0), b = min(ly + S, r1);
-    if (a < b) {
-      const int x0 = ceil_div_i(f.x - half + 1, os);
-      const int phx = x0 * os - f.x + half - 1, phy = y0 * os - f.y + half - 1;
-      const int k = __builtin_amdgcn_readfirstlane(perm[i]);
+  // Metadata of 64 rows is fetched lane-parallel in one coalesced load and broadcast per row with
+  // readlane, so walking the item costs one memory latency per 64 rows, not two per row.
+  for (int blk = it.start; blk < it.end && r0 < r1; blk += 64) {
+    const int mine = blk + lane;
+    int m_ly = -1 << 20, m_lx = 0, m_ph = 0, m_k = 0;
+    if (mine < it.end) {
+      const int2 f = fine[mine];
+      const int x0 = ceil_div_i(f.x - half + 1, os), y0 = ceil_div_i(f.y - half + 1, os);
+      m_ly = y0 - it.oy;
+      m_lx = x0 - it.ox;
+      m_ph = (y0 * os - f.y + half - 1) * os + (x0 * os - f.x + half - 1);
+      m_k = perm[mine];
+    }
+    float2 m_v[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+      m_v[c] = (mine < it.end) ? vis[static_cast<size_t>(m_k) * NP + c] : make_float2(0.0f, 0.0f);
+    const int nrow = min(64, it.end - blk);
+    for (int j = 0; j < nrow; ++j) {
+      const int ly = __builtin_amdgcn_readlane(m_ly, j);
+      const int a = max(ly, r0), b = min(ly + S, r1);
+      if (a >= b) continue;
+      const int lx = __builtin_amdgcn_readlane(m_lx, j);
+      const int ph = __builtin_amdgcn_readlane(m_ph, j);
       float2 v[NP];
 #pragma unroll
-      for (int c = 0; c < NP; ++c) v[c] = vis[static_cast<size_t>(k) * NP + c];
-      const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(phy * os + phx) * SS * NP * NP, SS);
-      const int lx = x0 - it.ox;
+      for (int c = 0; c < NP; ++c)
+        v[c] = make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_v[c].x), j)),
+                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_v[c].y), j)));
+      const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(ph) * SS * NP * NP, SS);
       const int cnt = (b - a) * S;
       const uint32_t t0 = static_cast<uint32_t>((a - ly) * S);
 #pragma unroll 2
@@ -259,12 +270,11 @@ __global__ __launch_bounds__(kThreads) void grid_banded_kernel(const Item* __res
         }
       }
     }
-    f = fn;
   }
   __syncthreads();
   const bool shift = (flags & PG_FFTSHIFT) != 0;
   const size_t pstride = static_cast<size_t>(n) * n;
-  for (int idx = threadIdx.x; idx < W * W; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < W * W; idx += (NW * 64)) {
     const int y = idx / W, x = idx - y * W;
     const int X = it.ox + x, Y = it.oy + y;
     if (X >= n || Y >= n) continue;
@@ -282,23 +292,56 @@ __global__ __launch_bounds__(kThreads) void grid_banded_kernel(const Item* __res
   }
 }
 
-template <int NP, typename TapT>
-__global__ __launch_bounds__(kThreads) void degrid_kernel(const Item* __restrict__ items,
-                                                          const int2* __restrict__ fine,
-                                                          const int32_t* __restrict__ perm,
-                                                          const TapT* __restrict__ table,
-                                                          const PlaneInfo* __restrict__ planes, int os, int n,
-                                                          const float2* __restrict__ grid,
-                                                          float2* __restrict__ vis_out, int flags) {
+template <int NP, typename TapT, int NW>
+__global__ __launch_bounds__(NW * 64) void grid_banded_kernel(const Item* __restrict__ items,
+                                                              const int2* __restrict__ fine,
+                                                              const int32_t* __restrict__ perm,
+                                                              const float2* __restrict__ vis,
+                                                              const TapT* __restrict__ table,
+                                                              const PlaneInfo* __restrict__ planes, int os, int n,
+                                                              float2* __restrict__ grid, int flags, int sub_bytes) {
   extern __shared__ float lds_f[];
+  grid_item_banded<NP, TapT, NW>(items[blockIdx.x], fine, perm, vis, table, planes, os, n, grid, flags, sub_bytes,
+                                 lds_f);
+}
+
+// Persistent form over many fields: each workgroup takes (field, item) pairs from a global queue
+// until it is empty; the queue is ordered largest item first.  Every workgroup leaves the loop
+// once the counter has passed n_work, so the grid drains without any waiting.
+template <int NP, typename TapT, int NW>
+__global__ __launch_bounds__(NW * 64) void grid_banded_persistent(const FieldArgs* __restrict__ fields,
+                                                                  const int2* __restrict__ work, int n_work,
+                                                                  int* __restrict__ counter, int flags,
+                                                                  int sub_bytes) {
+  extern __shared__ float lds_f[];
+  __shared__ int slot;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(counter, 1);
+    __syncthreads();
+    const int w = slot;
+    __syncthreads();
+    if (w >= n_work) break;
+    const int2 wr = work[w];
+    const FieldArgs fa = fields[wr.x];
+    grid_item_banded<NP, TapT, NW>(fa.items[wr.y], fa.fine, fa.perm, fa.vis, static_cast<const TapT*>(fa.table),
+                                   fa.planes, fa.os, fa.n, fa.grid, flags, sub_bytes, lds_f);
+    __syncthreads();
+  }
+}
+
+template <int NP, typename TapT, int NW>
+__device__ __forceinline__ void degrid_item(const Item it, const int2* __restrict__ fine,
+                                            const int32_t* __restrict__ perm, const TapT* __restrict__ table,
+                                            const PlaneInfo* __restrict__ planes, int os, int n,
+                                            const float2* __restrict__ grid, float2* __restrict__ vis_out,
+                                            int flags, float* lds_f) {
   float2* lds = reinterpret_cast<float2*>(lds_f);  // [q][W][P]
-  const Item it = items[blockIdx.x];
   const PlaneInfo pl = planes[it.plane];
   const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
   const float inv_s = 1.0f / static_cast<float>(S);
   const bool shift = (flags & PG_FFTSHIFT) != 0;
   const size_t pstride = static_cast<size_t>(n) * n;
-  for (int idx = threadIdx.x; idx < W * W; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < W * W; idx += (NW * 64)) {
     const int y = idx / W, x = idx - y * W;
     const int X = it.ox + x, Y = it.oy + y;
     const bool in = X < n && Y < n;
@@ -311,42 +354,89 @@ __global__ __launch_bounds__(kThreads) void degrid_kernel(const Item* __restrict
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = it.start + wave; i < it.end; i += kWaves) {
-    const int2 f = uniform(fine[i]);
-    const int k = __builtin_amdgcn_readfirstlane(perm[i]);
-    const int x0 = ceil_div_i(f.x - half + 1, os), y0 = ceil_div_i(f.y - half + 1, os);
-    const int phx = x0 * os - f.x + half - 1, phy = y0 * os - f.y + half - 1;
-    const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(phy * os + phx) * SS * NP * NP, SS);
-    const int lx = x0 - it.ox, ly = y0 - it.oy;
-    float acc[2 * NP];
+  // wave w takes rows start + w, start + w + NW, ...; metadata of 64 of them at a time comes in one
+  // coalesced load and is broadcast per row with readlane
+  for (int blk = it.start + wave; blk < it.end; blk += 64 * NW) {
+    const int mine = blk + lane * NW;
+    int m_ly = 0, m_lx = 0, m_ph = 0, m_k = 0;
+    if (mine < it.end) {
+      const int2 f = fine[mine];
+      const int x0 = ceil_div_i(f.x - half + 1, os), y0 = ceil_div_i(f.y - half + 1, os);
+      m_ly = y0 - it.oy;
+      m_lx = x0 - it.ox;
+      m_ph = (y0 * os - f.y + half - 1) * os + (x0 * os - f.x + half - 1);
+      m_k = perm[mine];
+    }
+    const int nrow = min(64, (it.end - blk + NW - 1) / NW);
+    for (int j = 0; j < nrow; ++j) {
+      const int ly = __builtin_amdgcn_readlane(m_ly, j);
+      const int lx = __builtin_amdgcn_readlane(m_lx, j);
+      const int ph = __builtin_amdgcn_readlane(m_ph, j);
+      const int k = __builtin_amdgcn_readlane(m_k, j);
+      const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(ph) * SS * NP * NP, SS);
+      float acc[2 * NP];
 #pragma unroll
-    for (int c = 0; c < 2 * NP; ++c) acc[c] = 0.0f;
+      for (int c = 0; c < 2 * NP; ++c) acc[c] = 0.0f;
 #pragma unroll 2
-    for (int t = lane; t < SS; t += 64) {
-      const int ty = static_cast<int>((static_cast<float>(t) + 0.5f) * inv_s);
-      const int tx = t - ty * S;
-      float2 tap[NP * NP];
-      tc.load(static_cast<uint32_t>(t), tap);
-      const int off = (ly + ty) * P + lx + tx;
+      for (int t = lane; t < SS; t += 64) {
+        const int ty = static_cast<int>((static_cast<float>(t) + 0.5f) * inv_s);
+        const int tx = t - ty * S;
+        float2 tap[NP * NP];
+        tc.load(static_cast<uint32_t>(t), tap);
+        const int off = (ly + ty) * P + lx + tx;
 #pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        const float2 g = lds[q * WP + off];
+        for (int q = 0; q < NP; ++q) {
+          const float2 g = lds[q * WP + off];
 #pragma unroll
-        for (int c = 0; c < NP; ++c) {
-          const float2 a = tap[q * NP + c];  // conj(a) * g
-          acc[2 * c] = fmaf(a.x, g.x, fmaf(a.y, g.y, acc[2 * c]));
-          acc[2 * c + 1] = fmaf(a.x, g.y, fmaf(-a.y, g.x, acc[2 * c + 1]));
+          for (int c = 0; c < NP; ++c) {
+            const float2 a = tap[q * NP + c];  // conj(a) * g
+            acc[2 * c] = fmaf(a.x, g.x, fmaf(a.y, g.y, acc[2 * c]));
+            acc[2 * c + 1] = fmaf(a.x, g.y, fmaf(-a.y, g.x, acc[2 * c + 1]));
+          }
         }
       }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < 2 * NP; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c)
+          vis_out[static_cast<size_t>(k) * NP + c] = make_float2(acc[2 * c], acc[2 * c + 1]);
+      }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int c = 0; c < 2 * NP; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < NP; ++c) vis_out[static_cast<size_t>(k) * NP + c] = make_float2(acc[2 * c], acc[2 * c + 1]);
-    }
+  }
+}
+
+template <int NP, typename TapT, int NW>
+__global__ __launch_bounds__(NW * 64) void degrid_kernel(const Item* __restrict__ items,
+                                                         const int2* __restrict__ fine,
+                                                         const int32_t* __restrict__ perm,
+                                                         const TapT* __restrict__ table,
+                                                         const PlaneInfo* __restrict__ planes, int os, int n,
+                                                         const float2* __restrict__ grid,
+                                                         float2* __restrict__ vis_out, int flags) {
+  extern __shared__ float lds_f[];
+  degrid_item<NP, TapT, NW>(items[blockIdx.x], fine, perm, table, planes, os, n, grid, vis_out, flags, lds_f);
+}
+
+template <int NP, typename TapT, int NW>
+__global__ __launch_bounds__(NW * 64) void degrid_persistent(const FieldArgs* __restrict__ fields,
+                                                             const int2* __restrict__ work, int n_work,
+                                                             int* __restrict__ counter, int flags) {
+  extern __shared__ float lds_f[];
+  __shared__ int slot;
+  for (;;) {
+    if (threadIdx.x == 0) slot = atomicAdd(counter, 1);
+    __syncthreads();
+    const int w = slot;
+    __syncthreads();
+    if (w >= n_work) break;
+    const int2 wr = work[w];
+    const FieldArgs fa = fields[wr.x];
+    degrid_item<NP, TapT, NW>(fa.items[wr.y], fa.fine, fa.perm, static_cast<const TapT*>(fa.table), fa.planes, fa.os,
+                              fa.n, fa.grid, fa.vis, flags, lds_f);
+    __syncthreads();
   }
 }
 
@@ -391,23 +481,35 @@ hipError_t allow_lds(F* fn, size_t bytes) {
                              static_cast<int>(bytes));
 }
 
+template <int NP, typename TapT, int NW>
+hipError_t run_grid_banded(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
+                           hipStream_t s) {
+  auto fn = grid_banded_kernel<NP, TapT, NW>;
+  const size_t bytes = k->lds_bytes + kBandScratch;
+  hipError_t e = allow_lds(fn, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(NW * 64), bytes, s, p->items.as<Item>(),
+                     p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(), k->planes.as<PlaneInfo>(),
+                     k->os, k->n, grid, flags, static_cast<int>(k->lds_bytes));
+  return hipGetLastError();
+}
+
 template <int NP, typename TapT>
 hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
                     hipStream_t s) {
   // Banded ownership needs enough sub-grid rows to give every wave a band; the LDS-atomic
-  // variant serves narrow sub-grids.  Either can be forced with a flag.
-  bool banded = k->max_width >= 2 * kWaves;
+  // variant serves narrow sub-grids.  The plan's launch setting or a call flag can force either.
+  bool banded = k->max_width >= 2 * p->grid_waves;
+  if (p->grid_variant == 1) banded = false;
+  if (p->grid_variant == 2) banded = true;
   if (flags & PG_VARIANT_ATOMIC) banded = false;
   if (flags & PG_VARIANT_BANDED) banded = true;
   if (banded) {
-    auto fn = grid_banded_kernel<NP, TapT>;
-    const size_t bytes = k->lds_bytes + kBandScratch;
-    hipError_t e = allow_lds(fn, bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(kThreads), bytes, s, p->items.as<Item>(),
-                       p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(), k->planes.as<PlaneInfo>(),
-                       k->os, k->n, grid, flags, static_cast<int>(k->lds_bytes));
-    return hipGetLastError();
+    switch (p->grid_waves) {
+      case 4: return run_grid_banded<NP, TapT, 4>(p, k, vis, grid, flags, s);
+      case 8: return run_grid_banded<NP, TapT, 8>(p, k, vis, grid, flags, s);
+      default: return run_grid_banded<NP, TapT, 16>(p, k, vis, grid, flags, s);
+    }
   }
   auto fn = grid_kernel<NP, TapT>;
   hipError_t e = allow_lds(fn, k->lds_bytes);
@@ -418,19 +520,110 @@ hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, fl
   return hipGetLastError();
 }
 
-template <int NP, typename TapT>
-hipError_t run_degrid(const pg_plan* p, const pg_kernels* k, const float2* grid, float2* vis, int flags,
-                      hipStream_t s) {
-  auto fn = degrid_kernel<NP, TapT>;
+template <int NP, typename TapT, int NW>
+hipError_t run_degrid_nw(const pg_plan* p, const pg_kernels* k, const float2* grid, float2* vis, int flags,
+                         hipStream_t s) {
+  auto fn = degrid_kernel<NP, TapT, NW>;
   hipError_t e = allow_lds(fn, k->lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(kThreads), k->lds_bytes, s,
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(NW * 64), k->lds_bytes, s,
                      p->items.as<Item>(), p->fine.as<int2>(), p->perm.as<int32_t>(), k->table.as<TapT>(),
                      k->planes.as<PlaneInfo>(), k->os, k->n, grid, vis, flags);
   return hipGetLastError();
 }
 
+template <int NP, typename TapT>
+hipError_t run_degrid(const pg_plan* p, const pg_kernels* k, const float2* grid, float2* vis, int flags,
+                      hipStream_t s) {
+  switch (p->degrid_waves) {
+    case 4: return run_degrid_nw<NP, TapT, 4>(p, k, grid, vis, flags, s);
+    case 8: return run_degrid_nw<NP, TapT, 8>(p, k, grid, vis, flags, s);
+    default: return run_degrid_nw<NP, TapT, 16>(p, k, grid, vis, flags, s);
+  }
+}
+
+// Workgroups that fit one CU at once, from LDS and from the 32-wave limit.
+inline int resident_wgs(size_t lds_bytes, int nw) {
+  const int by_lds = lds_bytes ? static_cast<int>(163840 / lds_bytes) : 32;
+  const int by_waves = 32 / nw;
+  return std::max(1, std::min(by_lds, by_waves));
+}
+
+template <int NP, typename TapT, int NW>
+hipError_t run_batch_grid(const pg_batch* b, int flags, hipStream_t s) {
+  auto fn = grid_banded_persistent<NP, TapT, NW>;
+  const size_t bytes = b->lds_bytes + kBandScratch;
+  hipError_t e = allow_lds(fn, bytes);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = std::min<int64_t>(b->n_work, static_cast<int64_t>(b->n_cus) * resident_wgs(bytes, NW));
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(NW * 64), bytes, s, b->fields.as<FieldArgs>(),
+                     b->work.as<int2>(), static_cast<int>(b->n_work), b->counter.as<int>(), flags,
+                     static_cast<int>(b->lds_bytes));
+  return hipGetLastError();
+}
+
+template <int NP, typename TapT, int NW>
+hipError_t run_batch_degrid(const pg_batch* b, int flags, hipStream_t s) {
+  auto fn = degrid_persistent<NP, TapT, NW>;
+  hipError_t e = allow_lds(fn, b->lds_bytes);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = std::min<int64_t>(b->n_work, static_cast<int64_t>(b->n_cus) * resident_wgs(b->lds_bytes, NW));
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(NW * 64), b->lds_bytes, s, b->fields.as<FieldArgs>(),
+                     b->work.as<int2>(), static_cast<int>(b->n_work), b->counter.as<int>(), flags);
+  return hipGetLastError();
+}
+
+template <int NP, typename TapT>
+hipError_t dispatch_batch(const pg_batch* b, int flags, hipStream_t s, bool grid) {
+  const int nw = grid ? b->grid_waves : b->degrid_waves;
+  if (grid) {
+    if (nw == 4) return run_batch_grid<NP, TapT, 4>(b, flags, s);
+    if (nw == 8) return run_batch_grid<NP, TapT, 8>(b, flags, s);
+    return run_batch_grid<NP, TapT, 16>(b, flags, s);
+  }
+  if (nw == 4) return run_batch_degrid<NP, TapT, 4>(b, flags, s);
+  if (nw == 8) return run_batch_degrid<NP, TapT, 8>(b, flags, s);
+  return run_batch_degrid<NP, TapT, 16>(b, flags, s);
+}
+
+hipError_t batch_body(const pg_batch* b, int flags, hipStream_t s, bool grid) {
+  const bool f16 = b->storage == PG_STORE_F16;
+  if (b->npol == 4) return f16 ? dispatch_batch<4, __half2>(b, flags, s, grid) : dispatch_batch<4, float2>(b, flags, s, grid);
+  return f16 ? dispatch_batch<1, __half2>(b, flags, s, grid) : dispatch_batch<1, float2>(b, flags, s, grid);
+}
+
 }  // namespace
+
+hipError_t launch_batch_grid(const pg_batch* b, int flags, hipStream_t s) {
+  for (int f = 0; f < b->nfields; ++f) {
+    if (!(flags & PG_ACCUMULATE)) {
+      const pg_kernels* k = b->kernels[f];
+      hipError_t e = launch_fill_zero(b->grids[f], static_cast<size_t>(k->npol) * k->n * k->n * sizeof(float2), s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  if (b->n_work == 0) return hipSuccess;
+  hipError_t e = launch_fill_zero(b->counter.p, 8, s);
+  if (e != hipSuccess) return e;
+  return batch_body(b, flags, s, true);
+}
+
+hipError_t launch_batch_degrid(const pg_batch* b, int flags, hipStream_t s) {
+  for (int f = 0; f < b->nfields; ++f) {
+    const pg_plan* p = b->plans[f];
+    if (p->nvis > p->n_kept) {
+      const int64_t nd = p->nvis - p->n_kept;
+      hipLaunchKernelGGL(zero_dropped, dim3(static_cast<unsigned>((nd + 255) / 256)), dim3(256), 0, s,
+                         p->perm.as<int32_t>(), p->n_kept, p->nvis, b->npol, static_cast<float2*>(b->vis[f]));
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  if (b->n_work == 0) return hipSuccess;
+  hipError_t e = launch_fill_zero(b->counter.p, 8, s);
+  if (e != hipSuccess) return e;
+  return batch_body(b, flags, s, false);
+}
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 8;

@@ -4,6 +4,7 @@
 // Mueller cell), and packing into the [phase_y][phase_x][tap_y][tap_x][q][c]
 // table the gridder reads.
 #include "common.hpp"
+#include "mlp.hpp"
 
 namespace pg {
 namespace {
@@ -143,7 +144,36 @@ __global__ void pack_kernel(const double2* __restrict__ t, int support, int os, 
   }
 }
 
+// One Mueller cell of one plane from a dense [phase_y][phase_x][tap_y][tap_x][re, im] float array
+// into the chunk-major table.
+__global__ void write_cell_kernel(void* __restrict__ table, int storage, int nqc, int ce, int os, int support,
+                                  int64_t plane_offset, int qc, const float* __restrict__ src) {
+  const size_t ss = static_cast<size_t>(support) * support;
+  const size_t total = ss * os * os;
+  const size_t nch = nqc / ce, ch = qc / ce, e = qc % ce;
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t phase = i / ss, tap = i % ss;
+    const size_t dst = plane_offset + ((phase * nch + ch) * ss + tap) * ce + e;
+    const float re = src[2 * i], im = src[2 * i + 1];
+    if (storage == PG_STORE_F16) {
+      static_cast<__half2*>(table)[dst] = __floats2half2_rn(re, im);
+    } else {
+      static_cast<float2*>(table)[dst] = make_float2(re, im);
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t write_cell(void* table, int storage, int nqc, int ce, int os, int support, int64_t plane_offset, int qc,
+                      const float* src, hipStream_t s) {
+  const size_t total = static_cast<size_t>(support) * support * os * os;
+  const int blocks = static_cast<int>(std::min<size_t>((total + 255) / 256, 65535));
+  hipLaunchKernelGGL(write_cell_kernel, dim3(blocks), dim3(256), 0, s, table, storage, nqc, ce, os, support,
+                     plane_offset, qc, src);
+  return hipGetLastError();
+}
 
 hipError_t launch_screen(const double2* phi, const double* aa_lat, double w, double fov, int mk, int nqc,
                          double2* out, hipStream_t s) {

@@ -1,0 +1,21 @@
+// Device launchers of the kernel-surrogate network (mlp.hip).  bf16 values are uint16_t bit patterns.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pg {
+hipError_t mlp_gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
+                    int64_t sbn, float* C, int64_t ldc, bool accumulate, int split_k, hipStream_t s);
+hipError_t mlp_bias_act(float* y, const float* b, int64_t rows, int64_t cols, bool silu, uint16_t* act, hipStream_t s);
+hipError_t mlp_silu_back(const float* gact, const float* z, int64_t n, float* gpre, uint16_t* gpre_bf, hipStream_t s);
+hipError_t mlp_loss(const float* y, const float* t, int64_t cols, int batch, float* grad, uint16_t* grad_bf,
+                    float* loss, hipStream_t s);
+hipError_t mlp_colsum(const float* g, int64_t rows, int64_t cols, float* out, hipStream_t s);
+hipError_t mlp_adam(float* w, uint16_t* w_bf, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                    float b2, float eps, int64_t step, hipStream_t s);
+hipError_t mlp_to_bf16(const float* x, int64_t n, uint16_t* out, hipStream_t s);
+hipError_t mlp_init_uniform(float* w, int64_t n, uint64_t seed, float a, hipStream_t s);
+hipError_t write_cell(void* table, int storage, int nqc, int ce, int os, int support, int64_t plane_offset, int qc,
+                      const float* src, hipStream_t s);
+}  // namespace pg

@@ -1,0 +1,230 @@
+// C-ABI of the kernel-surrogate network: creation, forward, one training step (forward, loss,
+// backward, Adam), parameter and activation access, and writing a generated kernel into a table.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "mlp.hpp"
+
+struct pg_mlp {
+  int32_t n_in = 0, width = 0, hidden = 0, max_batch = 0;
+  int64_t n_out = 0;
+  int64_t step = 0;
+  std::vector<int64_t> dims;  // d_0 = n_in, d_1..d_hidden = width, d_{hidden+1} = n_out
+  struct Layer {
+    pg::DevBuf w, w_bf, b, gw, gb, mw, vw, mb, vb;
+  };
+  std::vector<Layer> layers;          // layers[l] maps d_l -> d_{l+1}
+  pg::DevBuf x_bf;                    // [B][n_in] bf16
+  std::vector<pg::DevBuf> pre, act;   // pre[l] float [B][d_{l+1}], act[l] bf16 [B][d_{l+1}] (hidden only)
+  pg::DevBuf gy, gy_bf, ga, gz, gz_bf, loss;
+  int32_t last_batch = 0;
+};
+
+namespace pg {
+void set_error(const std::string& msg);
+}
+
+namespace {
+int fail(int code, const std::string& m) {
+  pg::set_error(m);
+  return code;
+}
+#define PGM_HIP(call, what)                                                                    \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail(PG_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int forward_impl(pg_mlp* m, const float* x, int batch, hipStream_t s) {
+  const int L = static_cast<int>(m->layers.size());
+  PGM_HIP(pg::mlp_to_bf16(x, static_cast<int64_t>(batch) * m->n_in, m->x_bf.as<uint16_t>(), s), "features");
+  const uint16_t* a = m->x_bf.as<uint16_t>();
+  for (int l = 0; l < L; ++l) {
+    const int64_t din = m->dims[l], dout = m->dims[l + 1];
+    float* z = m->pre[l].as<float>();
+    PGM_HIP(pg::mlp_gemm(batch, static_cast<int>(dout), static_cast<int>(din), a, din, 1, m->layers[l].w_bf.as<uint16_t>(),
+                         dout, 1, z, dout, false, 1, s), "forward gemm");
+    const bool hidden = l + 1 < L;
+    PGM_HIP(pg::mlp_bias_act(z, m->layers[l].b.as<float>(), batch, dout, hidden, hidden ? m->act[l].as<uint16_t>() : nullptr, s),
+            "bias/activation");
+    if (hidden) a = m->act[l].as<uint16_t>();
+  }
+  m->last_batch = batch;
+  return PG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pg_mlp_create(int32_t n_in, int32_t width, int32_t hidden_layers, int64_t n_out, int32_t max_batch, uint64_t seed,
+                  void* stream, pg_mlp** out) {
+  pg::set_error("");
+  if (!out) return fail(PG_EINVAL, "out must be non-NULL");
+  *out = nullptr;
+  if (n_in < 1 || n_in > 4096 || width < 1 || width > 8192 || hidden_layers < 1 || hidden_layers > 16 || n_out < 1 ||
+      n_out > (int64_t(1) << 30) || max_batch < 1 || max_batch > 65536)
+    return fail(PG_EINVAL, "bad network shape");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* m = new (std::nothrow) pg_mlp();
+  if (!m) return fail(PG_ENOMEM, "host allocation failed");
+  std::unique_ptr<pg_mlp> guard(m);
+  m->n_in = n_in;
+  m->width = width;
+  m->hidden = hidden_layers;
+  m->n_out = n_out;
+  m->max_batch = max_batch;
+  m->dims.push_back(n_in);
+  for (int i = 0; i < hidden_layers; ++i) m->dims.push_back(width);
+  m->dims.push_back(n_out);
+  const int L = hidden_layers + 1;
+  m->layers.resize(L);
+  m->pre.resize(L);
+  m->act.resize(L);
+  const int64_t B = max_batch;
+  for (int l = 0; l < L; ++l) {
+    const int64_t din = m->dims[l], dout = m->dims[l + 1], nw = din * dout;
+    auto& ly = m->layers[l];
+    if (!ly.w.alloc(4 * nw, s) || !ly.w_bf.alloc(2 * nw, s) || !ly.b.alloc(4 * dout, s) || !ly.gw.alloc(4 * nw, s) ||
+        !ly.gb.alloc(4 * dout, s) || !ly.mw.alloc(4 * nw, s) || !ly.vw.alloc(4 * nw, s) || !ly.mb.alloc(4 * dout, s) ||
+        !ly.vb.alloc(4 * dout, s) || !m->pre[l].alloc(4 * B * dout, s))
+      return fail(PG_ENOMEM, "device allocation failed in mlp_create");
+    if (l + 1 < L && !m->act[l].alloc(2 * B * dout, s)) return fail(PG_ENOMEM, "device allocation failed in mlp_create");
+    const float a = static_cast<float>(std::sqrt((l + 1 < L ? 6.0 : 3.0) / static_cast<double>(din)));
+    PGM_HIP(pg::mlp_init_uniform(ly.w.as<float>(), nw, seed + (static_cast<uint64_t>(l) << 40), a, s), "init");
+    PGM_HIP(pg::mlp_to_bf16(ly.w.as<float>(), nw, ly.w_bf.as<uint16_t>(), s), "init bf16");
+    for (pg::DevBuf* z : {&ly.b, &ly.mw, &ly.vw, &ly.mb, &ly.vb, &ly.gb})
+      PGM_HIP(pg::launch_fill_zero(z->p, z->bytes, s), "zero");
+  }
+  const int64_t wmax = *std::max_element(m->dims.begin() + 1, m->dims.end() - 1);
+  if (!m->x_bf.alloc(2 * B * n_in + 16, s) || !m->gy.alloc(4 * B * n_out, s) || !m->gy_bf.alloc(2 * B * n_out + 16, s) ||
+      !m->ga.alloc(4 * B * wmax, s) || !m->gz.alloc(4 * B * wmax, s) || !m->gz_bf.alloc(2 * B * wmax + 16, s) ||
+      !m->loss.alloc(8, s))
+    return fail(PG_ENOMEM, "device allocation failed in mlp_create");
+  PGM_HIP(hipStreamSynchronize(s), "mlp sync");
+  *out = guard.release();
+  return PG_OK;
+}
+
+int pg_mlp_forward(pg_mlp* m, const float* x, int32_t batch, float* y, void* stream) {
+  pg::set_error("");
+  if (!m || !x) return fail(PG_EINVAL, "network and features must be non-NULL");
+  if (batch < 1 || batch > m->max_batch) return fail(PG_EINVAL, "batch must be in [1, max_batch]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = forward_impl(m, x, batch, s);
+  if (rc != PG_OK) return rc;
+  if (y)
+    PGM_HIP(hipMemcpyAsync(y, m->pre.back().p, 4 * static_cast<int64_t>(batch) * m->n_out, hipMemcpyDeviceToDevice, s),
+            "copy output");
+  return PG_OK;
+}
+
+int pg_mlp_train_step(pg_mlp* m, const float* x, const float* target, int32_t batch, float lr, int32_t update,
+                      float* loss_out, void* stream) {
+  pg::set_error("");
+  if (!m || !x || !target) return fail(PG_EINVAL, "network, features and targets must be non-NULL");
+  if (batch < 1 || batch > m->max_batch) return fail(PG_EINVAL, "batch must be in [1, max_batch]");
+  if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(PG_EINVAL, "learning rate must be finite and >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = forward_impl(m, x, batch, s);
+  if (rc != PG_OK) return rc;
+  const int L = static_cast<int>(m->layers.size());
+  PGM_HIP(pg::launch_fill_zero(m->loss.p, 8, s), "zero loss");
+  PGM_HIP(pg::mlp_loss(m->pre.back().as<float>(), target, m->n_out, batch, m->gy.as<float>(), m->gy_bf.as<uint16_t>(),
+                       m->loss.as<float>(), s), "loss");
+  // backward: g_z of layer l in (gz_f, gz_b); the output layer's is the loss gradient
+  const float* gz_f = m->gy.as<float>();
+  const uint16_t* gz_b = m->gy_bf.as<uint16_t>();
+  for (int l = L - 1; l >= 0; --l) {
+    const int64_t din = m->dims[l], dout = m->dims[l + 1];
+    const uint16_t* a_in = l == 0 ? m->x_bf.as<uint16_t>() : m->act[l - 1].as<uint16_t>();
+    // gW[din][dout] = a_in^T g_z ; contraction over the batch
+    PGM_HIP(pg::mlp_gemm(static_cast<int>(din), static_cast<int>(dout), batch, a_in, 1, din, gz_b, dout, 1,
+                         m->layers[l].gw.as<float>(), dout, false, 1, s), "weight gradient");
+    PGM_HIP(pg::mlp_colsum(gz_f, batch, dout, m->layers[l].gb.as<float>(), s), "bias gradient");
+    if (l > 0) {
+      // g_a[B][din] = g_z W^T ; contraction over dout (split for the wide output layer)
+      const int split = dout >= 16384 ? static_cast<int>(std::min<int64_t>(256, dout / 4096)) : 1;
+      PGM_HIP(pg::mlp_gemm(batch, static_cast<int>(din), static_cast<int>(dout), gz_b, dout, 1,
+                           m->layers[l].w_bf.as<uint16_t>(), 1, dout, m->ga.as<float>(), din, false, split, s),
+              "input gradient");
+      PGM_HIP(pg::mlp_silu_back(m->ga.as<float>(), m->pre[l - 1].as<float>(), static_cast<int64_t>(batch) * din,
+                                m->gz.as<float>(), m->gz_bf.as<uint16_t>(), s), "silu backward");
+      gz_f = m->gz.as<float>();
+      gz_b = m->gz_bf.as<uint16_t>();
+    }
+  }
+  if (update) {
+    m->step += 1;
+    for (int l = 0; l < L; ++l) {
+      auto& ly = m->layers[l];
+      const int64_t nw = m->dims[l] * m->dims[l + 1];
+      PGM_HIP(pg::mlp_adam(ly.w.as<float>(), ly.w_bf.as<uint16_t>(), ly.gw.as<float>(), ly.mw.as<float>(),
+                           ly.vw.as<float>(), nw, lr, 0.9f, 0.999f, 1e-8f, m->step, s), "adam");
+      PGM_HIP(pg::mlp_adam(ly.b.as<float>(), nullptr, ly.gb.as<float>(), ly.mb.as<float>(), ly.vb.as<float>(),
+                           m->dims[l + 1], lr, 0.9f, 0.999f, 1e-8f, m->step, s), "adam");
+    }
+  }
+  if (loss_out) PGM_HIP(hipMemcpyAsync(loss_out, m->loss.p, 4, hipMemcpyDeviceToDevice, s), "copy loss");
+  return PG_OK;
+}
+
+int pg_mlp_copy(const pg_mlp* m, int32_t what, int32_t layer, void* dst, void* stream) {
+  pg::set_error("");
+  if (!m || !dst) return fail(PG_EINVAL, "network and dst must be non-NULL");
+  const int L = static_cast<int>(m->layers.size());
+  if (layer < 0 || layer >= L) return fail(PG_EINVAL, "layer out of range");
+  const auto& ly = m->layers[layer];
+  const int64_t din = m->dims[layer], dout = m->dims[layer + 1], B = m->last_batch;
+  const void* src = nullptr;
+  int64_t bytes = 0;
+  switch (what) {
+    case PG_MLP_W: src = ly.w.p; bytes = 4 * din * dout; break;
+    case PG_MLP_W_BF16: src = ly.w_bf.p; bytes = 2 * din * dout; break;
+    case PG_MLP_B: src = ly.b.p; bytes = 4 * dout; break;
+    case PG_MLP_GW: src = ly.gw.p; bytes = 4 * din * dout; break;
+    case PG_MLP_GB: src = ly.gb.p; bytes = 4 * dout; break;
+    case PG_MLP_ACT: src = layer == 0 ? m->x_bf.p : m->act[layer - 1].p; bytes = 2 * B * din; break;
+    case PG_MLP_PRE: src = m->pre[layer].p; bytes = 4 * B * dout; break;
+    case PG_MLP_GY: src = m->gy.p; bytes = 4 * B * m->n_out; break;
+    case PG_MLP_GY_BF16: src = m->gy_bf.p; bytes = 2 * B * m->n_out; break;
+    case PG_MLP_GZ: src = m->gz.p; bytes = 4 * B * m->dims[1]; break;
+    case PG_MLP_GZ_BF16: src = m->gz_bf.p; bytes = 2 * B * m->dims[1]; break;
+    default: return fail(PG_EINVAL, "unknown quantity");
+  }
+  PGM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)), "copy");
+  return PG_OK;
+}
+
+int pg_mlp_load(pg_mlp* m, int32_t layer, const float* w, const float* b, void* stream) {
+  pg::set_error("");
+  if (!m || !w || !b) return fail(PG_EINVAL, "network, w and b must be non-NULL");
+  if (layer < 0 || layer >= static_cast<int>(m->layers.size())) return fail(PG_EINVAL, "layer out of range");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto& ly = m->layers[layer];
+  const int64_t nw = m->dims[layer] * m->dims[layer + 1];
+  PGM_HIP(hipMemcpyAsync(ly.w.p, w, 4 * nw, hipMemcpyDeviceToDevice, s), "load w");
+  PGM_HIP(hipMemcpyAsync(ly.b.p, b, 4 * m->dims[layer + 1], hipMemcpyDeviceToDevice, s), "load b");
+  PGM_HIP(pg::mlp_to_bf16(ly.w.as<float>(), nw, ly.w_bf.as<uint16_t>(), s), "load bf16");
+  return PG_OK;
+}
+
+void pg_mlp_destroy(pg_mlp* m) { delete m; }
+
+int pg_kernels_write_cell(pg_kernels* k, int32_t plane, int32_t q, int32_t c, const float* src, void* stream) {
+  pg::set_error("");
+  if (!k || !src) return fail(PG_EINVAL, "kernels and src must be non-NULL");
+  if (plane < 0 || plane >= k->nplanes || q < 0 || q >= k->npol || c < 0 || c >= k->npol)
+    return fail(PG_EINVAL, "plane or Mueller cell out of range");
+  const int nqc = k->npol * k->npol;
+  PGM_HIP(pg::write_cell(k->table.p, k->storage, nqc, pg::chunk_entries(k->storage, nqc), k->os, k->support[plane],
+                         k->plane_offset[plane], q * k->npol + c, src, static_cast<hipStream_t>(stream)),
+          "write cell");
+  return PG_OK;
+}
+
+}  // extern "C"

@@ -45,6 +45,10 @@ class PgPlanDesc(ctypes.Structure):
                 ("perm", c_void_p), ("fine", c_void_p), ("items", c_void_p)]
 
 
+class PgField(ctypes.Structure):
+    _fields_ = [("plan", c_void_p), ("kernels", c_void_p), ("vis", c_void_p), ("grid", c_void_p)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
 
@@ -60,9 +64,24 @@ EXPORTS = {
     "pg_plan_info": (c_int, [c_void_p, POINTER(PgPlanDesc)]),
     "pg_plan_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pg_plan_destroy": (None, [c_void_p]),
+    "pg_plan_set_launch": (c_int, [c_void_p, c_int32, c_int32, c_int32]),
     "pg_grid": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "pg_degrid": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "pg_taper": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]),
+    "pg_batch_create": (c_int, [POINTER(PgField), c_int32, c_void_p, POINTER(c_void_p)]),
+    "pg_batch_grid": (c_int, [c_void_p, c_int32, c_void_p]),
+    "pg_batch_degrid": (c_int, [c_void_p, c_int32, c_void_p]),
+    "pg_batch_work_items": (c_int64, [c_void_p]),
+    "pg_batch_destroy": (None, [c_void_p]),
+    "pg_kernels_write_cell": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "pg_mlp_create": (c_int, [c_int32, c_int32, c_int32, c_int64, c_int32, ctypes.c_uint64, c_void_p,
+                              POINTER(c_void_p)]),
+    "pg_mlp_forward": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "pg_mlp_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_int32, c_void_p,
+                                  c_void_p]),
+    "pg_mlp_copy": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+    "pg_mlp_load": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "pg_mlp_destroy": (None, [c_void_p]),
 }
 
 _lib = None
@@ -142,6 +161,9 @@ def _geometry_struct(geom):
     return g, (w, s, t)
 
 
+MLP_W, MLP_W_BF16, MLP_B, MLP_GW, MLP_GB, MLP_ACT, MLP_PRE, MLP_GY, MLP_GY_BF16, MLP_GZ, MLP_GZ_BF16 = range(11)
+
+
 class Kernels:
     """A kernel table set (pg_kernels)."""
 
@@ -170,6 +192,10 @@ class Kernels:
             out = torch.empty(n, dtype=torch.complex64, device="cuda")
         _check(lib().pg_kernels_copy_table(self._h, _ptr(out), _stream()))
         return out
+
+    def write_cell(self, plane: int, q: int, c: int, src, stream=None):
+        """Overwrite cell (q, c) of `plane` from device float [os][os][S][S][2]."""
+        _check(lib().pg_kernels_write_cell(self._h, int(plane), int(q), int(c), _ptr(src), _stream(stream)))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -215,6 +241,11 @@ class Plan:
         items = torch.empty((max(self.n_items, 1), 8), dtype=torch.int32, device="cuda")
         _check(lib().pg_plan_copy(self._h, _ptr(perm), _ptr(fine), _ptr(items), _stream()))
         return perm[:self.nvis], fine[:self.n_kept], items[:self.n_items]
+
+    def set_launch(self, grid_variant: int = 0, grid_waves: int = 16, degrid_waves: int = 16):
+        """Launch tuning (grid variant 0 auto / 1 atomic / 2 banded, waves per workgroup)."""
+        _check(lib().pg_plan_set_launch(self._h, int(grid_variant), int(grid_waves), int(degrid_waves)))
+        return self
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -291,3 +322,86 @@ def predict(p: Plan, k: Kernels, model, out=None, buf=None):
     taper(k, model, buf, TAPER_PREDICT)
     g = torch.fft.ifft2(buf, norm="forward")
     return degrid(p, k, g, out=out, fftshift=True)
+
+
+class Batch:
+    """Many fields gridded or degridded by one persistent launch (pg_batch)."""
+
+    def __init__(self, fields, stream=None):
+        self._keep = list(fields)
+        arr = (PgField * len(fields))()
+        for i, (p, k, vis, g) in enumerate(fields):
+            arr[i] = PgField(p.handle, k.handle, vis.data_ptr() if vis is not None else None, g.data_ptr())
+        h = c_void_p()
+        _check(lib().pg_batch_create(arr, len(fields), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.work_items = int(lib().pg_batch_work_items(self._h))
+
+    def grid(self, fftshift: bool = False, accumulate: bool = False, stream=None):
+        flags = (FFTSHIFT if fftshift else 0) | (ACCUMULATE if accumulate else 0)
+        _check(lib().pg_batch_grid(self._h, flags, _stream(stream)))
+
+    def degrid(self, fftshift: bool = False, stream=None):
+        _check(lib().pg_batch_degrid(self._h, FFTSHIFT if fftshift else 0, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pg_batch_destroy(self._h)
+            self._h = None
+
+
+def batch(fields, stream=None) -> Batch:
+    """fields: list of (Plan, Kernels, vis tensor, grid tensor) sharing npol and table storage."""
+    return Batch(fields, stream)
+
+
+class MLP:
+    """Kernel surrogate network (pg_mlp): BF16 matrix-core products, FP32 masters, Adam."""
+
+    def __init__(self, n_in: int, width: int, hidden: int, n_out: int, max_batch: int, seed: int = 1, stream=None):
+        h = c_void_p()
+        _check(lib().pg_mlp_create(int(n_in), int(width), int(hidden), int(n_out), int(max_batch),
+                                   ctypes.c_uint64(int(seed)), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.dims = [n_in] + [width] * hidden + [n_out]
+        self.max_batch = max_batch
+
+    def forward(self, x, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device=x.device)
+        _check(lib().pg_mlp_forward(self._h, _ptr(x), int(x.shape[0]), _ptr(out), _stream(stream)))
+        return out
+
+    def train_step(self, x, target, lr: float, update: bool = True, stream=None):
+        import torch
+
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        _check(lib().pg_mlp_train_step(self._h, _ptr(x), _ptr(target), int(x.shape[0]), ctypes.c_float(lr),
+                                       1 if update else 0, _ptr(loss), _stream(stream)))
+        return loss
+
+    def copy(self, what: int, layer: int, batch: int = 0):
+        """A parameter, gradient or activation of `layer` as a device tensor."""
+        import torch
+
+        din, dout = self.dims[layer], self.dims[layer + 1]
+        shapes = {MLP_W: ((din, dout), torch.float32), MLP_W_BF16: ((din, dout), torch.bfloat16),
+                  MLP_B: ((dout,), torch.float32), MLP_GW: ((din, dout), torch.float32),
+                  MLP_GB: ((dout,), torch.float32), MLP_ACT: ((batch, din), torch.bfloat16),
+                  MLP_PRE: ((batch, dout), torch.float32), MLP_GY: ((batch, self.dims[-1]), torch.float32),
+                  MLP_GY_BF16: ((batch, self.dims[-1]), torch.bfloat16), MLP_GZ: ((batch, self.dims[1]), torch.float32),
+                  MLP_GZ_BF16: ((batch, self.dims[1]), torch.bfloat16)}
+        shape, dt = shapes[what]
+        out = torch.empty(shape, dtype=dt, device="cuda")
+        _check(lib().pg_mlp_copy(self._h, int(what), int(layer), _ptr(out), _stream()))
+        return out
+
+    def load(self, layer: int, w, b):
+        _check(lib().pg_mlp_load(self._h, int(layer), _ptr(w.contiguous()), _ptr(b.contiguous()), _stream()))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pg_mlp_destroy(self._h)
+            self._h = None

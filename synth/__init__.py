@@ -76,7 +76,7 @@ def lds_pitch(width: int, support: int) -> int:
     return width + (support - width) % 32
 
 
-def default_tiles(support, q, lds_bytes=163840 - 1152):
+def default_tiles(support, q, lds_bytes=163840 - 1280):
     """Largest tile T per plane whose (T+S-1) x pitch x q complex64 sub-grid fits lds_bytes."""
     out = []
     for s in np.asarray(support):
@@ -288,3 +288,35 @@ def scaled_config2(nvis: int, n: int = 256, nplanes: int = 8, seed: int = SEED_B
                       tile=np.asarray(tile, dtype=np.int32), aa_support=g.aa_support, mk=mk)
     w.name = f"c2-fullpol-AW-{n}"
     return w
+
+
+def config3(seed: int = SEED_BASE + 3, nfields: int = 16, n: int = 4096, cell: float = 3.5 * ARCSEC,
+            nplanes: int = 32, vis_lo: int = 100_000, vis_hi: int = 4_000_000, mk: int = 256,
+            count_scale: float = 1.0) -> list:
+    """Batched: nfields channels 700-1800 MHz, each with its own grid, beam and visibility count.
+
+    Counts are log-uniform in [vis_lo, vis_hi] (times count_scale); each field is the 36-antenna
+    array tracked over 8 h with count/630 dumps at its own frequency; the power-beam FWHM is
+    1 deg x 1.4 GHz / nu; the cell keeps the field of view (and so the supports) of config 2.
+    """
+    rng = np.random.default_rng(seed)
+    enu = antennas_in_disk(36, 1500.0, rng)
+    counts = np.exp(rng.uniform(math.log(vis_lo), math.log(vis_hi), nfields))
+    counts = np.maximum(1, (counts * count_scale).astype(np.int64))
+    nbl = 36 * 35 // 2
+    out = []
+    for i in range(nfields):
+        nu = 700e6 + i * 1100e6 / max(1, nfields - 1)
+        ndump = max(1, -(-int(counts[i]) // nbl))
+        ha = np.linspace(-4.0, 4.0, ndump) * (15.0 * DEG)
+        uvw = uvw_tracks(enu, ASKAP_LAT, -45.0 * DEG, ha, nu)[:int(counts[i])]
+        fov = n * cell
+        w_max = max(100.0, math.ceil(np.abs(uvw[:, 2]).max() / 100.0) * 100.0)
+        planes = linear_w_planes(nplanes, w_max)
+        support = support_rule(planes, fov)
+        geom = Geometry(n=n, cell=cell, os=8, w_planes=planes, support=support,
+                        tile=default_tiles(support, 4), aa_support=7, mk=mk)
+        beam = seeded_leakage_beam(1.0 * DEG * 1.4e9 / nu, rng)
+        out.append(Workload(f"c3-field{i:02d}-{nu / 1e6:.0f}MHz", geom, uvw, 4, beam=beam,
+                            extra={"freq_hz": nu}))
+    return out

@@ -1,5 +1,6 @@
 """Parity at the full full-pol workload (2048^2 x 4, 32 planes, supports 16-48, os 8, 2.3M rows),
-in the launch configuration the benchmark times (max_chunk 1024, centring folded into grid/degrid).
+in the launch configuration the benchmark times (the autotuned tiles, chunk length and waves per
+workgroup, centring folded into grid/degrid).
 
 The oracle cannot grid 2.3M rows in seconds, so: the plan is compared bit-exactly in full; grid
 and degrid are compared on a seeded sample of rows drawn from three planes (the densest plane, a
@@ -19,7 +20,6 @@ pg = pytest.importorskip("paper_2206_15117_amd.polgrid")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-MAX_CHUNK = 1024
 
 
 def rel(a, b):
@@ -28,13 +28,16 @@ def rel(a, b):
 
 @pytest.fixture(scope="module")
 def full():
+    from paper_2206_15117_amd import autotune
+
     w = synth.config2()
-    g = w.geom
+    g, chunk, _, gw, dw = autotune.apply(w.geom, 4, pg.STORE_F32)
+    w.geom = g
     jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
     kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=w.eps_null)
     kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones)
     uvw = torch.from_numpy(w.uvw).cuda()
-    p = pg.plan(kg, uvw, max_chunk=MAX_CHUNK)
+    p = pg.plan(kg, uvw, max_chunk=chunk).set_launch(0, gw, dw)
     loc = geometry.locate(g, w.uvw)
     counts = np.bincount(loc["plane"], minlength=g.nplanes)
     dense = int(np.argmax(counts))
@@ -48,12 +51,12 @@ def full():
     td = kernels.make_tables(g, mueller.phi_degrid(jones), planes=planes)
     n = g.n
     sign = ((-1.0) ** (np.arange(n)[:, None] + np.arange(n)[None, :]))[None]
-    return dict(w=w, kg=kg, kd=kd, uvw=uvw, p=p, sample=np.sort(sample), tg=tg, td=td, sign=sign)
+    return dict(w=w, kg=kg, kd=kd, uvw=uvw, p=p, sample=np.sort(sample), tg=tg, td=td, sign=sign, chunk=chunk)
 
 
 def test_full_plan_bit_exact(full):
     w, p = full["w"], full["p"]
-    want = oplan.plan(w.geom, w.uvw, MAX_CHUNK)
+    want = oplan.plan(w.geom, w.uvw, full["chunk"])
     perm, fine, items = (t.cpu().numpy() for t in p.arrays())
     assert (p.n_kept, p.n_dropped, p.n_items) == (want["n_kept"], want["n_dropped"], want["items"].shape[0])
     assert np.array_equal(perm, want["perm"])

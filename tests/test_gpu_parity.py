@@ -200,6 +200,21 @@ def test_c2_grid_parity(c2_case, max_chunk, variant):
         assert rel(got[q], want[q]) < TOL, q
 
 
+@pytest.mark.parametrize("waves", [4, 8, 16])
+def test_c2_launch_shapes(c2_case, waves):
+    """Every waves-per-workgroup setting of the banded grid and the degrid gives the oracle result."""
+    w, vis, tg, td, kg, kd = c2_case
+    rng = np.random.default_rng(40 + waves)
+    g = (rng.standard_normal((4, 256, 256)) + 1j * rng.standard_normal((4, 256, 256))).astype(np.complex64)
+    p = pg.plan(kg, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves)
+    got = host(pg.grid(p, kg, dev(vis)))
+    want = gridding.grid(w.geom, tg, w.uvw, vis)
+    assert rel(got, want) < TOL
+    pd = pg.plan(kd, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves)
+    gv = host(pg.degrid(pd, kd, dev(g)))
+    assert rel(gv, gridding.degrid(w.geom, td, w.uvw, g)) < TOL
+
+
 def test_c2_degrid_parity(c2_case):
     w, _, _, td, _, kd = c2_case
     rng = np.random.default_rng(4)
