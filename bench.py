@@ -39,6 +39,12 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=450000)
     ap.add_argument("--grid-variant", choices=["auto", "atomic", "banded"], default="auto")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-field section")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-kernel section")
+    ap.add_argument("--surrogate-kernels", type=int, default=200_000,
+                    help="teacher kernels the network is trained on")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="before warm-up, run one elementwise pass over 256 MiB (read 256 MiB, write 256 MiB) "
+                         "whose HBM counters scale FETCH_SIZE / WRITE_SIZE of the other kernels")
     return ap.parse_args()
 
 
@@ -80,9 +86,10 @@ def main():
 
     w = synth.config2(nvis=args.nvis)
     # launch shape from the autotuner cache (tiles per plane, chunk length, waves per workgroup)
-    g, max_chunk, tuned_variant, gw, dw = autotune.apply(w.geom, 4, pg.STORE_F32)
+    launch = autotune.apply(w.geom, 4, pg.STORE_F32)
     if args.max_chunk:
-        max_chunk = args.max_chunk
+        launch = launch._replace(max_chunk=args.max_chunk)
+    g, max_chunk, tuned_variant, gw, dw = launch[:5]
     if variant == 0:
         variant = {1: pg.VARIANT_ATOMIC, 2: pg.VARIANT_BANDED}.get(tuned_variant, 0)
     jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
@@ -102,7 +109,7 @@ def main():
     ii = np.clip(np.round(w.src_m / g.cell).astype(int) + n // 2, 0, n - 1)
     for s in range(len(jj)):
         model[:, ii[s], jj[s]] += torch.from_numpy(w.src_iquv[s].astype(np.float32)).cuda()
-    p0 = pg.plan(kd, uvw, max_chunk=max_chunk).set_launch(0, gw, dw)
+    p0 = autotune.plan(kd, uvw, launch)
     vis = pg.predict(p0, kd, model)
     del p0
 
@@ -116,7 +123,7 @@ def main():
         e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         if record:
             e[0].record()
-        p = pg.plan(kg, uvw, max_chunk=max_chunk).set_launch(0, gw, dw)
+        p = autotune.plan(kg, uvw, launch)
         if record:
             e[1].record()
         pg.grid(p, kg, vis, out=grid_buf, fftshift=True, variant=variant)
@@ -137,6 +144,12 @@ def main():
             ev["degrid"].append((e[3], e[4]))
         return p
 
+    if args.calibrate_copy:
+        x = torch.ones((64 << 20,), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        torch.neg(x, out=torch.empty_like(x))
+        torch.cuda.synchronize()
+        del x
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -169,9 +182,11 @@ def main():
         "config": {"workload": "full-pol A+W 2048x2048x4, 32 w-planes, support 16-48, os 8, "
                                "Gaussian 1deg beam + 1% leakage, 36 ant / 630 baselines, 2.3M rows",
                    "nvis": w.nvis, "n_kept": p.n_kept, "n_items": p.n_items, "max_chunk": max_chunk,
-                   "grid_waves": gw, "degrid_waves": dw, "tiles": [int(t) for t in g.tile],
+                   "grid_waves": gw, "degrid_waves": dw, "xcd_group": launch.xcd_group,
+                   "tiles": [int(t) for t in g.tile],
                    "mean_support_sq": s2_sum / max(p.n_kept, 1)},
         "breakdown_ms": ms, "make_kernels_s": t_kernels,
+        "rows_per_s_grid_plus_degrid": w.nvis / ((ms["grid"] + ms["degrid"]) * 1e-3),
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic,
                      "hbm_frac_alg": bytes_alg / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS},
@@ -181,6 +196,9 @@ def main():
         del grid_buf, fft_buf, img, vis_out
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(max(2, args.steps // 2), 1)
+    if not args.no_surrogate:
+        torch.cuda.empty_cache()
+        out["surrogate"] = bench_surrogate(args.surrogate_kernels)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -204,14 +222,14 @@ def bench_batched(steps, warmup):
     from paper_2206_15117_amd import autotune
 
     for w in fields:
-        g, chunk, _, gw, dw = autotune.apply(w.geom, 4, pg.STORE_F16)
+        launch = autotune.apply(w.geom, 4, pg.STORE_F16)
+        g = launch.geom
         jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
         kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=0.2, storage=pg.STORE_F16)
         kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones, storage=pg.STORE_F16)
         uvw = torch.from_numpy(w.uvw).cuda()
         ks.append((kg, kd))
-        ps.append((pg.plan(kg, uvw, max_chunk=chunk).set_launch(0, gw, dw),
-                   pg.plan(kd, uvw, max_chunk=chunk).set_launch(0, gw, dw)))
+        ps.append((autotune.plan(kg, uvw, launch), autotune.plan(kd, uvw, launch)))
         vis.append(torch.from_numpy(synth.random_vis(w.nvis, 4, rng)).cuda())
         outs.append(torch.empty((w.nvis, 4), dtype=torch.complex64, device="cuda"))
     torch.cuda.synchronize()
@@ -279,6 +297,109 @@ def bench_batched(steps, warmup):
             "hip_graph": True, "work_items": bg.work_items + bd.work_items,
             "grid_ms": ev[0].elapsed_time(ev[1]), "degrid_ms": ev[2].elapsed_time(ev[3]),
             "setup_s": t_setup, "image_rel_err_f16_vs_f32": err}
+
+
+def bench_surrogate(n_kernels):
+    """Learned A x W kernels on the config-1 grid (256^2, 0.1 rad) with 48 x 48 taps x 8 x 8
+    phases: train the network on n_kernels FFT-generated kernels (random w, frequency, parallactic
+    angle, all 16 Mueller cells), then report generation rate against the FFT generator, held-out
+    kernel error, and image errors against images made with FFT kernels."""
+    import torch
+
+    import synth
+    from paper_2206_15117_amd import polgrid as pg
+    from paper_2206_15117_amd import surrogate as sg
+
+    s = synth.config4()
+    g = s.geom
+    scale = sg.cell_scale(sg.Teacher(s, synth.jones_on_lattice, planes=16, seed=1), 2)
+    planes = 8
+    teacher = sg.Teacher(s, synth.jones_on_lattice, planes=planes, seed=1)
+    calls = -(-n_kernels // (planes * sg.N_CELLS))
+    x, c, basis, info = sg.teacher_data(teacher, scale, calls, basis_calls=32, rank=256)
+    t0 = time.perf_counter()
+    net_r, losses = sg.train_coefficients(x, c, steps=20000, batch=2048, lr=5e-3)
+    net = sg.fold(net_r, basis)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del x, c
+    err = sg.heldout_error(net, sg.Teacher(s, synth.jones_on_lattice, planes=16, seed=999), scale, calls=4)
+
+    # generation rate: one 32-plane kernel set (512 cells) per (nu, pa)
+    w32 = np.linspace(-s.w_max, s.w_max, 32)
+    jones = synth.jones_on_lattice(s.beam(s.nu_eval, s.pa_eval), g.mk, g.fov)
+    g32 = s.plane_geometry(w32)
+    sg.surrogate_kernels(net, s, w32, s.nu_eval, s.pa_eval, scale)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sg.surrogate_kernels(net, s, w32, s.nu_eval, s.pa_eval, scale)
+    torch.cuda.synchronize()
+    t_mlp = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pg.make_kernels(g32, 4, pg.KIND_GRID, jones=jones, eps_null=0.2)
+    torch.cuda.synchronize()
+    t_fft = (time.perf_counter() - t0) / reps
+
+    # images of the config-1 uv coverage and sky through the beam at (nu, pa): network kernels
+    # against FFT kernels, and per-channel kernels against one channel-averaged kernel set
+    uvw = torch.from_numpy(s.uvw).cuda()
+
+    def image_with(ks, vis_list):
+        grid = torch.zeros((4, g.n, g.n), dtype=torch.complex64, device="cuda")
+        tot = 0
+        for k, v in zip(ks, vis_list):
+            p = pg.plan(k, uvw, max_chunk=256)
+            pg.grid(p, k, v, out=grid, accumulate=True, fftshift=True)
+            tot += p.n_kept
+        out = torch.empty((4, g.n, g.n), dtype=torch.float32, device="cuda")
+        return pg.taper(ks[0], torch.fft.fft2(grid), out, pg.TAPER_IMAGE, float(tot))
+
+    def model_vis(nu, pa):
+        # the sky predicted through this channel's degridding kernels
+        kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=synth.jones_on_lattice(s.beam(nu, pa), g.mk, g.fov))
+        model = torch.zeros((4, g.n, g.n), dtype=torch.float32, device="cuda")
+        jj = np.clip(np.round(s.src_l / g.cell).astype(int) + g.n // 2, 0, g.n - 1)
+        ii = np.clip(np.round(s.src_m / g.cell).astype(int) + g.n // 2, 0, g.n - 1)
+        for k in range(len(jj)):
+            model[:, ii[k], jj[k]] += torch.from_numpy(s.src_iquv[k].astype(np.float32)).cuda()
+        return pg.predict(pg.plan(kd, uvw, max_chunk=256), kd, model)
+
+    inner = torch.zeros((g.n, g.n), dtype=torch.bool, device="cuda")
+    inner[g.n // 4:3 * g.n // 4, g.n // 4:3 * g.n // 4] = True
+
+    def rms(a, ref, peak):
+        return float((a[:, inner] - ref[:, inner]).pow(2).mean().sqrt() / peak)
+
+    v0 = model_vis(s.nu_eval, s.pa_eval)
+    k_fft = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=0.2)
+    k_mlp = sg.surrogate_kernels(net, s, g.w_planes, s.nu_eval, s.pa_eval, scale)
+    i_fft, i_mlp = image_with([k_fft], [v0]), image_with([k_mlp], [v0])
+    peak = float(i_fft[0][inner].abs().max())
+    chans = [700e6, 1000e6, 1300e6, 1600e6]
+    jl = [synth.jones_on_lattice(s.beam(nu, s.pa_eval), g.mk, g.fov) for nu in chans]
+    vl = [model_vis(nu, s.pa_eval) for nu in chans]
+    i_chan_fft = image_with([pg.make_kernels(g, 4, pg.KIND_GRID, jones=j, eps_null=0.2) for j in jl], vl)
+    i_chan_mlp = image_with([sg.surrogate_kernels(net, s, g.w_planes, nu, s.pa_eval, scale) for nu in chans], vl)
+    k_avg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=sum(jl) / len(jl), eps_null=0.2)
+    i_chan_avg = image_with([k_avg] * len(chans), vl)
+    peak4 = float(i_chan_fft[0][inner].abs().max())
+    return {"workload": "kernel network 24 features -> 3 x 256 SiLU -> 294912 (48x48 taps x 8x8 phases, complex), "
+                        "bf16 weights, fp32 accumulate; teacher = FFT generator on the 256^2 / 0.1 rad grid, "
+                        "w in [-200, 200], 700-1800 MHz, pa in [-pi, pi]",
+            "kernels_trained": info["kernels"], "teacher_calls": calls, "teacher_s": info["teacher_s"],
+            "train_s": t_train, "train_steps": 20000, "final_loss": losses[-1][1],
+            "basis_rank": info["rank"], "basis_residual_heldout": info["basis_residual_heldout"],
+            "heldout_rel_err_mean": float(err.mean()), "heldout_rel_err_per_cell": [float(e) for e in err],
+            "kernels_per_s_network": 512 / t_mlp, "kernels_per_s_fft_generator": 512 / t_fft,
+            "image_rms_vs_fft_kernels": rms(i_mlp, i_fft, peak),
+            "image_rms_vs_fft_kernels_stokes_I": rms(i_mlp[:1], i_fft[:1], peak),
+            "four_channels_rms_vs_per_channel_fft": {
+                "network_per_channel": rms(i_chan_mlp, i_chan_fft, peak4),
+                "channel_averaged_beam": rms(i_chan_avg, i_chan_fft, peak4)},
+            "note": "image errors: rms over the inner half of the field / Stokes-I peak of the FFT-kernel image"}
 
 
 def cpu_baseline(w, nsample):

@@ -135,7 +135,8 @@ const char* pg_last_error(void);
 
 /* Device memory hooks.  alloc(bytes, stream, ctx) returns device memory or NULL;
  * free(ptr, stream, ctx) releases it.  Passing NULL restores hipMalloc/hipFree.
- * Applies to objects created afterwards. */
+ * Applies to objects created afterwards; every object frees through the hooks it was created
+ * with, so the hook functions and ctx must stay valid until those objects are destroyed. */
 void pg_set_allocator(void* (*alloc_fn)(size_t, void*, void*),
                       void (*free_fn)(void*, void*, void*), void* ctx);
 
@@ -169,9 +170,12 @@ void pg_plan_destroy(pg_plan* p);
 
 /* Launch tuning of the kernels that run over this plan (results are unchanged up to float32
  * summation order): grid_variant 0 = choose by sub-grid width, 1 = LDS-atomic accumulation,
- * 2 = row-band ownership; grid_waves and degrid_waves = waves per workgroup, 4, 8 or 16.
- * Set before the plan is shared between threads.  Errors: PG_EINVAL. */
-int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves);
+ * 2 = row-band ownership; grid_waves and degrid_waves = waves per workgroup, 4, 8 or 16;
+ * xcd_group = how many consecutive work items (in plan order) run on one XCD, so that they share
+ * its L2 (1 = plain order, up to 4096).  Set before the plan is shared between threads.
+ * Errors: PG_EINVAL. */
+int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves,
+                       int32_t xcd_group);
 
 /* Gridding (Sec. 3.2, Sec. 4):
  *   G_q(X,Y) (+)= sum_k sum_c T_{p_k,q,c}(X os - fine_x,k, Y os - fine_y,k) V_{k,c}.
@@ -191,6 +195,26 @@ int pg_degrid(const pg_plan* p, const pg_kernels* k, const void* grid, void* vis
  * storage.  Used to run the gridder on generated (e.g. learned) kernels; call before the kernel
  * set is shared.  Enqueue only.  Errors: PG_EINVAL. */
 int pg_kernels_write_cell(pg_kernels* k, int32_t plane, int32_t q, int32_t c, const float* src, void* stream);
+
+/* A kernel set with the geometry, storage, anti-aliasing taper and plane layout that
+ * pg_make_kernels would give for `spec`, whose table is all zeros instead of generated (Jones
+ * field, eps_null and stokes_convention are not used).  It is filled by pg_kernels_import, e.g.
+ * with learned kernels, and then grids and degrids like any other kernel set.  Synchronises
+ * `stream`.  Errors: as pg_make_kernels. */
+int pg_kernels_alloc(const pg_kernel_spec* spec, void* stream, pg_kernels** out);
+
+/* Every Mueller cell of planes plane0 .. plane0 + nplanes - 1 as plain float32 device data:
+ * dst is [nplanes][npol (q)][npol (c)][os (phase_y)][os (phase_x)][S][S][re, im], the same
+ * (phase, tap) convention as the table definition above (Sec. 3.2 kernels).  The planes must share
+ * one support S.  Enqueue only.  Errors: PG_EINVAL (range, mixed supports, NULL). */
+int pg_kernels_export(const pg_kernels* k, int32_t plane0, int32_t nplanes, float* dst, void* stream);
+
+/* The inverse of pg_kernels_export: overwrite every cell of planes plane0 .. plane0 + nplanes - 1
+ * with cell_scale[q npol + c] x src (src device float32, layout as above; cell_scale host,
+ * npol^2 values, or NULL for 1), rounded to the table's storage.  Call before the kernel set is
+ * shared.  Enqueue only.  Errors: PG_EINVAL. */
+int pg_kernels_import(pg_kernels* k, int32_t plane0, int32_t nplanes, const float* src, const float* cell_scale,
+                      void* stream);
 
 /* ------------------------------------------------------------------ kernel surrogate network
  * A multilayer perceptron that emits one oversampled kernel cell from a feature vector: hidden

@@ -4,7 +4,8 @@ Searches, per geometry class (npol, storage, os, per-plane supports):
   * workgroups per CU (1-4): sets each plane's tile T to the largest sub-grid that fits
     1/k of the LDS, so every item of a launch has the same LDS footprint;
   * waves per workgroup for grid and degrid (4, 8, 16);
-  * the grid variant (row bands or LDS atomics) and the chunk length of work items.
+  * the grid variant (row bands or LDS atomics) and the chunk length of work items;
+  * how many consecutive work items share one XCD (and its L2), for the best shape found.
 Each candidate is timed with HIP events on a representative workload; the best choice is
 cached in tuning.json beside this file and read back by `tuned_config`.
 """
@@ -13,8 +14,11 @@ from __future__ import annotations
 import json
 import os
 import time
+from collections import namedtuple
 
 import numpy as np
+
+Launch = namedtuple("Launch", "geom max_chunk variant grid_waves degrid_waves xcd_group")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
@@ -73,19 +77,27 @@ def tuned_config(npol, storage, os_, support):
     return None
 
 
-def apply(geom, npol, storage):
-    """(geometry with tuned tiles, max_chunk, grid variant, grid waves, degrid waves) for this
-    geometry, using the grid direction's tiles for both directions when they differ."""
+def apply(geom, npol, storage) -> Launch:
+    """Launch(geometry with tuned tiles, max_chunk, grid variant, grid waves, degrid waves, XCD group)
+    for this geometry, using the grid direction's tiles for both directions when they differ."""
     import copy
 
     cfg = tuned_config(npol, storage, geom.os, geom.support)
     g = copy.copy(geom)
     if cfg is None:
-        return g, 1024, 0, 16, 16
+        return Launch(g, 1024, 0, 16, 16, 1)
     g.tile = np.asarray(cfg["grid"]["tiles"], dtype=np.int32)
     same = cfg["grid"]["wgs_per_cu"] == cfg["degrid"]["wgs_per_cu"]
-    return (g, int(cfg["grid"]["max_chunk"]), int(cfg["grid"].get("variant", 2)), int(cfg["grid"]["waves"]),
-            int(cfg["degrid"]["waves"]) if same else 16)
+    return Launch(g, int(cfg["grid"]["max_chunk"]), int(cfg["grid"].get("variant", 2)), int(cfg["grid"]["waves"]),
+                  int(cfg["degrid"]["waves"]) if same else 16, int(cfg.get("xcd_group", 1)))
+
+
+def plan(kernels, uvw, launch: Launch):
+    """A plan binned for `kernels` with the tuned chunk length and launch shape."""
+    from . import polgrid as pg
+
+    return pg.plan(kernels, uvw, max_chunk=launch.max_chunk).set_launch(0, launch.grid_waves, launch.degrid_waves,
+                                                                        launch.xcd_group)
 
 
 def _time(fn, reps):
@@ -141,6 +153,22 @@ def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2
                           variant=bg["variant"], ms=bg["grid_ms"], tiles=bg["tiles"]),
                 degrid=dict(wgs_per_cu=bd["wgs_per_cu"], max_chunk=bd["max_chunk"], waves=bd["waves"],
                             ms=bd["degrid_ms"], tiles=bd["tiles"]))
+    # XCD grouping for the best grid shape: sum of grid and degrid time
+    g = copy.copy(geom)
+    g.tile = np.asarray(bg["tiles"], dtype=np.int32)
+    kg = pg.make_kernels(g, npol, pg.KIND_GRID, jones=jones, eps_null=eps_null, storage=storage)
+    kd = pg.make_kernels(g, npol, pg.KIND_DEGRID, jones=jones, storage=storage)
+    p = pg.plan(kg, uvw, max_chunk=bg["max_chunk"])
+    best_x = (float("inf"), 1)
+    for xg in (1, 2, 4, 8, 16, 32):
+        p.set_launch(bg["variant"], bg["waves"], bd["waves"], xg)
+        t = (_time(lambda: pg.grid(p, kg, vis, out=grid, fftshift=True), reps)
+             + _time(lambda: pg.degrid(p, kd, grid, out=out, fftshift=True), reps))
+        results.append(dict(xcd_group=xg, grid_plus_degrid_ms=t))
+        if verbose:
+            print(json.dumps(results[-1]), flush=True)
+        best_x = min(best_x, (t, xg))
+    best["xcd_group"] = best_x[1]
     return best, results
 
 

@@ -70,7 +70,7 @@ Allocator current_allocator() {
 
 namespace {
 
-int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** out) {
+int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** out, bool generate) {
   if (!spec || !out) return fail(PG_EINVAL, "spec and out must be non-NULL");
   *out = nullptr;
   if (spec->npol != 1 && spec->npol != 4) return fail(PG_EINVAL, "npol must be 1 or 4");
@@ -87,7 +87,7 @@ int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** ou
   const int mk = g.mk, np = spec->npol, nqc = np * np;
   std::vector<double> phi;
   std::string err;
-  if (!build_screens(np, spec->kind, spec->jones, mk, spec->eps_null, spec->stokes_convention, phi, err))
+  if (generate && !build_screens(np, spec->kind, spec->jones, mk, spec->eps_null, spec->stokes_convention, phi, err))
     return fail(PG_EINVAL, err);
 
   auto* k = new (std::nothrow) pg_kernels();
@@ -132,21 +132,28 @@ int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** ou
   for (int j = 0; j < g.n; ++j) inv_aa[j] = 1.0 / k->aa_pixels[j];
 
   const size_t entry = spec->storage == PG_STORE_F16 ? 4 : 8;
-  const size_t npix = static_cast<size_t>(mk) * mk;
-  const size_t lmax = static_cast<size_t>(smax) * g.os;
-  DevBuf phi_d, aa_d, f_d, e_d, a_d, t_d;
   if (!k->table.alloc(k->plane_offset.back() * entry, s) || !k->planes.alloc(sizeof(PlaneInfo) * g.nplanes, s) ||
-      !k->w_dev.alloc(sizeof(double) * g.nplanes, s) || !k->inv_aa.alloc(sizeof(double) * g.n, s) ||
-      !phi_d.alloc(sizeof(double2) * nqc * npix, s) || !aa_d.alloc(sizeof(double) * mk, s) ||
-      !f_d.alloc(sizeof(double2) * nqc * npix, s) || !e_d.alloc(sizeof(double2) * lmax * mk, s) ||
-      !a_d.alloc(sizeof(double2) * nqc * mk * lmax, s) || !t_d.alloc(sizeof(double2) * nqc * lmax * lmax, s))
+      !k->w_dev.alloc(sizeof(double) * g.nplanes, s) || !k->inv_aa.alloc(sizeof(double) * g.n, s))
     return fail(PG_ENOMEM, "device allocation failed in make_kernels");
-
-  PG_HIP(hipMemcpyAsync(phi_d.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice, s), "upload screens");
-  PG_HIP(hipMemcpyAsync(aa_d.p, aa_lat.data(), mk * sizeof(double), hipMemcpyHostToDevice, s), "upload AA");
   PG_HIP(hipMemcpyAsync(k->planes.p, pinfo.data(), pinfo.size() * sizeof(PlaneInfo), hipMemcpyHostToDevice, s), "upload planes");
   PG_HIP(hipMemcpyAsync(k->w_dev.p, k->w_planes.data(), g.nplanes * sizeof(double), hipMemcpyHostToDevice, s), "upload w");
   PG_HIP(hipMemcpyAsync(k->inv_aa.p, inv_aa.data(), g.n * sizeof(double), hipMemcpyHostToDevice, s), "upload taper");
+  if (!generate) {
+    PG_HIP(hipMemsetAsync(k->table.p, 0, k->table.bytes, s), "clear table");
+    PG_HIP(hipStreamSynchronize(s), "kernels_alloc sync");
+    *out = guard.release();
+    return PG_OK;
+  }
+
+  const size_t npix = static_cast<size_t>(mk) * mk;
+  const size_t lmax = static_cast<size_t>(smax) * g.os;
+  DevBuf phi_d, aa_d, f_d, e_d, a_d, t_d;
+  if (!phi_d.alloc(sizeof(double2) * nqc * npix, s) || !aa_d.alloc(sizeof(double) * mk, s) ||
+      !f_d.alloc(sizeof(double2) * nqc * npix, s) || !e_d.alloc(sizeof(double2) * lmax * mk, s) ||
+      !a_d.alloc(sizeof(double2) * nqc * mk * lmax, s) || !t_d.alloc(sizeof(double2) * nqc * lmax * lmax, s))
+    return fail(PG_ENOMEM, "device allocation failed in make_kernels");
+  PG_HIP(hipMemcpyAsync(phi_d.p, phi.data(), phi.size() * sizeof(double), hipMemcpyHostToDevice, s), "upload screens");
+  PG_HIP(hipMemcpyAsync(aa_d.p, aa_lat.data(), mk * sizeof(double), hipMemcpyHostToDevice, s), "upload AA");
   const double fov = g.n * g.cell;
   for (int p = 0; p < g.nplanes; ++p) {
     const int S = g.support[p];
@@ -269,9 +276,18 @@ void pg_set_allocator(void* (*alloc_fn)(size_t, void*, void*), void (*free_fn)(v
 int pg_make_kernels(const pg_kernel_spec* spec, void* stream, pg_kernels** out) {
   g_error.clear();
   try {
-    return make_kernels_impl(spec, static_cast<hipStream_t>(stream), out);
+    return make_kernels_impl(spec, static_cast<hipStream_t>(stream), out, true);
   } catch (...) {
     return fail(PG_ENOMEM, "exception in make_kernels");
+  }
+}
+
+int pg_kernels_alloc(const pg_kernel_spec* spec, void* stream, pg_kernels** out) {
+  g_error.clear();
+  try {
+    return make_kernels_impl(spec, static_cast<hipStream_t>(stream), out, false);
+  } catch (...) {
+    return fail(PG_ENOMEM, "exception in kernels_alloc");
   }
 }
 
@@ -336,12 +352,15 @@ int pg_plan_copy(const pg_plan* p, int32_t* perm, int32_t* fine, int32_t* items,
 
 void pg_plan_destroy(pg_plan* p) { delete p; }
 
-int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves) {
+int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves,
+                       int32_t xcd_group) {
   g_error.clear();
   if (!p) return fail(PG_EINVAL, "plan must be non-NULL");
   if (grid_variant < 0 || grid_variant > 2) return fail(PG_EINVAL, "grid_variant must be 0, 1 or 2");
   auto ok = [](int w) { return w == 4 || w == 8 || w == 16; };
   if (!ok(grid_waves) || !ok(degrid_waves)) return fail(PG_EINVAL, "waves per workgroup must be 4, 8 or 16");
+  if (xcd_group < 1 || xcd_group > 4096) return fail(PG_EINVAL, "xcd_group must be in [1, 4096]");
+  p->xcd_group = xcd_group;
   p->grid_variant = grid_variant;
   p->grid_waves = grid_waves;
   p->degrid_waves = degrid_waves;

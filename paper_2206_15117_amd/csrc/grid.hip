@@ -81,15 +81,34 @@ struct TapChunks {
   }
 };
 
+// Workgroup -> work item map that keeps `group` consecutive items (one plane, neighbouring tiles,
+// so the same kernel-table rows and overlapping sub-grid halos) on one XCD and its L2.  The
+// hardware hands workgroups to the 8 XCDs round-robin (block b to XCD b mod 8), so block b =
+// 8 j + x takes item (8 (j / group) + x) group + j mod group: a bijection of [0, 8 group m).
+// group = 1 is the identity.  Launches pad the grid to a multiple of 8 group blocks.
+__device__ __forceinline__ int xcd_item(int b, int group) {
+  const int x = b & 7, j = b >> 3;
+  return ((j / group) * 8 + x) * group + (j % group);
+}
+
+inline unsigned xcd_blocks(int64_t n_items, int group) {
+  if (group <= 1) return static_cast<unsigned>(n_items);
+  const int64_t span = 8LL * group;
+  return static_cast<unsigned>((n_items + span - 1) / span * span);
+}
+
 template <int NP, typename TapT>
 __global__ __launch_bounds__(kThreads) void grid_kernel(const Item* __restrict__ items, const int2* __restrict__ fine,
                                                         const int32_t* __restrict__ perm,
                                                         const float2* __restrict__ vis,
                                                         const TapT* __restrict__ table,
                                                         const PlaneInfo* __restrict__ planes, int os, int n,
-                                                        float2* __restrict__ grid, int flags) {
+                                                        float2* __restrict__ grid, int flags, int n_items,
+                                                        int group) {
   extern __shared__ float lds[];  // [q][re|im][W][P]
-  const Item it = items[blockIdx.x];
+  const int item = xcd_item(blockIdx.x, group);
+  if (item >= n_items) return;
+  const Item it = items[item];
   const PlaneInfo pl = planes[it.plane];
   const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
   const float inv_s = 1.0f / static_cast<float>(S);
@@ -299,10 +318,12 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_kernel(const Item* __rest
                                                               const float2* __restrict__ vis,
                                                               const TapT* __restrict__ table,
                                                               const PlaneInfo* __restrict__ planes, int os, int n,
-                                                              float2* __restrict__ grid, int flags, int sub_bytes) {
+                                                              float2* __restrict__ grid, int flags, int sub_bytes,
+                                                              int n_items, int group) {
   extern __shared__ float lds_f[];
-  grid_item_banded<NP, TapT, NW>(items[blockIdx.x], fine, perm, vis, table, planes, os, n, grid, flags, sub_bytes,
-                                 lds_f);
+  const int item = xcd_item(blockIdx.x, group);
+  if (item >= n_items) return;
+  grid_item_banded<NP, TapT, NW>(items[item], fine, perm, vis, table, planes, os, n, grid, flags, sub_bytes, lds_f);
 }
 
 // Persistent form over many fields: each workgroup takes (field, item) pairs from a global queue
@@ -415,9 +436,12 @@ __global__ __launch_bounds__(NW * 64) void degrid_kernel(const Item* __restrict_
                                                          const TapT* __restrict__ table,
                                                          const PlaneInfo* __restrict__ planes, int os, int n,
                                                          const float2* __restrict__ grid,
-                                                         float2* __restrict__ vis_out, int flags) {
+                                                         float2* __restrict__ vis_out, int flags, int n_items,
+                                                         int group) {
   extern __shared__ float lds_f[];
-  degrid_item<NP, TapT, NW>(items[blockIdx.x], fine, perm, table, planes, os, n, grid, vis_out, flags, lds_f);
+  const int item = xcd_item(blockIdx.x, group);
+  if (item >= n_items) return;
+  degrid_item<NP, TapT, NW>(items[item], fine, perm, table, planes, os, n, grid, vis_out, flags, lds_f);
 }
 
 template <int NP, typename TapT, int NW>
@@ -488,9 +512,10 @@ hipError_t run_grid_banded(const pg_plan* p, const pg_kernels* k, const float2* 
   const size_t bytes = k->lds_bytes + kBandScratch;
   hipError_t e = allow_lds(fn, bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(NW * 64), bytes, s, p->items.as<Item>(),
+  hipLaunchKernelGGL(fn, dim3(xcd_blocks(p->n_items, p->xcd_group)), dim3(NW * 64), bytes, s, p->items.as<Item>(),
                      p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(), k->planes.as<PlaneInfo>(),
-                     k->os, k->n, grid, flags, static_cast<int>(k->lds_bytes));
+                     k->os, k->n, grid, flags, static_cast<int>(k->lds_bytes), static_cast<int>(p->n_items),
+                     p->xcd_group);
   return hipGetLastError();
 }
 
@@ -514,9 +539,9 @@ hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, fl
   auto fn = grid_kernel<NP, TapT>;
   hipError_t e = allow_lds(fn, k->lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(kThreads), k->lds_bytes, s,
+  hipLaunchKernelGGL(fn, dim3(xcd_blocks(p->n_items, p->xcd_group)), dim3(kThreads), k->lds_bytes, s,
                      p->items.as<Item>(), p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(),
-                     k->planes.as<PlaneInfo>(), k->os, k->n, grid, flags);
+                     k->planes.as<PlaneInfo>(), k->os, k->n, grid, flags, static_cast<int>(p->n_items), p->xcd_group);
   return hipGetLastError();
 }
 
@@ -526,9 +551,10 @@ hipError_t run_degrid_nw(const pg_plan* p, const pg_kernels* k, const float2* gr
   auto fn = degrid_kernel<NP, TapT, NW>;
   hipError_t e = allow_lds(fn, k->lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(NW * 64), k->lds_bytes, s,
+  hipLaunchKernelGGL(fn, dim3(xcd_blocks(p->n_items, p->xcd_group)), dim3(NW * 64), k->lds_bytes, s,
                      p->items.as<Item>(), p->fine.as<int2>(), p->perm.as<int32_t>(), k->table.as<TapT>(),
-                     k->planes.as<PlaneInfo>(), k->os, k->n, grid, vis, flags);
+                     k->planes.as<PlaneInfo>(), k->os, k->n, grid, vis, flags, static_cast<int>(p->n_items),
+                     p->xcd_group);
   return hipGetLastError();
 }
 

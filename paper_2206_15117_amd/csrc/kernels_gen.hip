@@ -146,32 +146,55 @@ __global__ void pack_kernel(const double2* __restrict__ t, int support, int os, 
 
 // One Mueller cell of one plane from a dense [phase_y][phase_x][tap_y][tap_x][re, im] float array
 // into the chunk-major table.
-__global__ void write_cell_kernel(void* __restrict__ table, int storage, int nqc, int ce, int os, int support,
-                                  int64_t plane_offset, int qc, const float* __restrict__ src) {
+// Moves Mueller cells between a chunk-major table and a plain float buffer laid out
+// [plane][cell][phase_y][phase_x][tap_y][tap_x][re, im].  Planes plane0 .. plane0+nplanes-1 share
+// one support, so plane i starts os^2 S^2 nqc entries after plane i-1; cells are qc0 .. qc0+ncell-1.
+// to_table: table <- scale[qc] * buf (rounded to the storage type); else buf <- table.
+__global__ void cell_io_kernel(void* __restrict__ table, int storage, int nqc, int ce, int os, int support,
+                               int64_t offset0, int nplanes, int qc0, int ncell, float* __restrict__ buf,
+                               int to_table, CellScale scale) {
   const size_t ss = static_cast<size_t>(support) * support;
-  const size_t total = ss * os * os;
-  const size_t nch = nqc / ce, ch = qc / ce, e = qc % ce;
+  const size_t per_cell = ss * os * os;
+  const size_t total = per_cell * ncell * nplanes;
+  const size_t nch = nqc / ce;
+  const size_t plane_stride = per_cell * nqc;
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < total;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const size_t phase = i / ss, tap = i % ss;
-    const size_t dst = plane_offset + ((phase * nch + ch) * ss + tap) * ce + e;
-    const float re = src[2 * i], im = src[2 * i + 1];
-    if (storage == PG_STORE_F16) {
-      static_cast<__half2*>(table)[dst] = __floats2half2_rn(re, im);
+    const size_t r = i % per_cell, pc = i / per_cell;
+    const int qc = qc0 + static_cast<int>(pc % ncell);
+    const size_t plane = pc / ncell;
+    const size_t phase = r / ss, tap = r % ss;
+    const size_t ch = qc / ce, e = qc % ce;
+    const size_t dst = offset0 + plane * plane_stride + ((phase * nch + ch) * ss + tap) * ce + e;
+    if (to_table) {
+      const float re = buf[2 * i] * scale.v[qc], im = buf[2 * i + 1] * scale.v[qc];
+      if (storage == PG_STORE_F16) {
+        static_cast<__half2*>(table)[dst] = __floats2half2_rn(re, im);
+      } else {
+        static_cast<float2*>(table)[dst] = make_float2(re, im);
+      }
     } else {
-      static_cast<float2*>(table)[dst] = make_float2(re, im);
+      float2 v;
+      if (storage == PG_STORE_F16) {
+        v = __half22float2(static_cast<const __half2*>(table)[dst]);
+      } else {
+        v = static_cast<const float2*>(table)[dst];
+      }
+      buf[2 * i] = v.x;
+      buf[2 * i + 1] = v.y;
     }
   }
 }
 
 }  // namespace
 
-hipError_t write_cell(void* table, int storage, int nqc, int ce, int os, int support, int64_t plane_offset, int qc,
-                      const float* src, hipStream_t s) {
-  const size_t total = static_cast<size_t>(support) * support * os * os;
+hipError_t cell_io(void* table, int storage, int nqc, int ce, int os, int support, int64_t offset0, int nplanes,
+                   int qc0, int ncell, float* buf, bool to_table, const CellScale& scale, hipStream_t s) {
+  const size_t total = static_cast<size_t>(support) * support * os * os * ncell * nplanes;
+  if (total == 0) return hipSuccess;
   const int blocks = static_cast<int>(std::min<size_t>((total + 255) / 256, 65535));
-  hipLaunchKernelGGL(write_cell_kernel, dim3(blocks), dim3(256), 0, s, table, storage, nqc, ce, os, support,
-                     plane_offset, qc, src);
+  hipLaunchKernelGGL(cell_io_kernel, dim3(blocks), dim3(256), 0, s, table, storage, nqc, ce, os, support, offset0,
+                     nplanes, qc0, ncell, buf, to_table ? 1 : 0, scale);
   return hipGetLastError();
 }
 

@@ -16,6 +16,9 @@ hipError_t mlp_adam(float* w, uint16_t* w_bf, const float* g, float* m, float* v
                     float b2, float eps, int64_t step, hipStream_t s);
 hipError_t mlp_to_bf16(const float* x, int64_t n, uint16_t* out, hipStream_t s);
 hipError_t mlp_init_uniform(float* w, int64_t n, uint64_t seed, float a, hipStream_t s);
-hipError_t write_cell(void* table, int storage, int nqc, int ce, int os, int support, int64_t plane_offset, int qc,
-                      const float* src, hipStream_t s);
+struct CellScale {
+  float v[16];
+};
+hipError_t cell_io(void* table, int storage, int nqc, int ce, int os, int support, int64_t offset0, int nplanes,
+                   int qc0, int ncell, float* buf, bool to_table, const CellScale& scale, hipStream_t s);
 }  // namespace pg

@@ -40,6 +40,15 @@ int fail(int code, const std::string& m) {
     if (e_ != hipSuccess) return fail(PG_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Contraction split for a product whose 64 x 64 output tiles alone cannot fill the GPU: enough
+// slices for about 512 workgroups, each slice at least 256 deep.
+int split_for(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  if (tiles >= 512) return 1;
+  const int64_t split = std::min<int64_t>((512 + tiles - 1) / tiles, K / 256);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(split, 256)));
+}
+
 int forward_impl(pg_mlp* m, const float* x, int batch, hipStream_t s) {
   const int L = static_cast<int>(m->layers.size());
   PGM_HIP(pg::mlp_to_bf16(x, static_cast<int64_t>(batch) * m->n_in, m->x_bf.as<uint16_t>(), s), "features");
@@ -144,13 +153,14 @@ int pg_mlp_train_step(pg_mlp* m, const float* x, const float* target, int32_t ba
     const uint16_t* a_in = l == 0 ? m->x_bf.as<uint16_t>() : m->act[l - 1].as<uint16_t>();
     // gW[din][dout] = a_in^T g_z ; contraction over the batch
     PGM_HIP(pg::mlp_gemm(static_cast<int>(din), static_cast<int>(dout), batch, a_in, 1, din, gz_b, dout, 1,
-                         m->layers[l].gw.as<float>(), dout, false, 1, s), "weight gradient");
+                         m->layers[l].gw.as<float>(), dout, false, split_for(din, dout, batch), s),
+            "weight gradient");
     PGM_HIP(pg::mlp_colsum(gz_f, batch, dout, m->layers[l].gb.as<float>(), s), "bias gradient");
     if (l > 0) {
-      // g_a[B][din] = g_z W^T ; contraction over dout (split for the wide output layer)
-      const int split = dout >= 16384 ? static_cast<int>(std::min<int64_t>(256, dout / 4096)) : 1;
+      // g_a[B][din] = g_z W^T ; contraction over dout (split when the output is narrow)
       PGM_HIP(pg::mlp_gemm(batch, static_cast<int>(din), static_cast<int>(dout), gz_b, dout, 1,
-                           m->layers[l].w_bf.as<uint16_t>(), 1, dout, m->ga.as<float>(), din, false, split, s),
+                           m->layers[l].w_bf.as<uint16_t>(), 1, dout, m->ga.as<float>(), din, false,
+                           split_for(batch, din, dout), s),
               "input gradient");
       PGM_HIP(pg::mlp_silu_back(m->ga.as<float>(), m->pre[l - 1].as<float>(), static_cast<int64_t>(batch) * din,
                                 m->gz.as<float>(), m->gz_bf.as<uint16_t>(), s), "silu backward");
@@ -221,9 +231,53 @@ int pg_kernels_write_cell(pg_kernels* k, int32_t plane, int32_t q, int32_t c, co
   if (plane < 0 || plane >= k->nplanes || q < 0 || q >= k->npol || c < 0 || c >= k->npol)
     return fail(PG_EINVAL, "plane or Mueller cell out of range");
   const int nqc = k->npol * k->npol;
-  PGM_HIP(pg::write_cell(k->table.p, k->storage, nqc, pg::chunk_entries(k->storage, nqc), k->os, k->support[plane],
-                         k->plane_offset[plane], q * k->npol + c, src, static_cast<hipStream_t>(stream)),
+  pg::CellScale one;
+  for (float& v : one.v) v = 1.0f;
+  PGM_HIP(pg::cell_io(k->table.p, k->storage, nqc, pg::chunk_entries(k->storage, nqc), k->os, k->support[plane],
+                      k->plane_offset[plane], 1, q * k->npol + c, 1, const_cast<float*>(src), true, one,
+                      static_cast<hipStream_t>(stream)),
           "write cell");
+  return PG_OK;
+}
+
+namespace {
+int check_plane_range(const pg_kernels* k, int32_t plane0, int32_t nplanes) {
+  if (plane0 < 0 || nplanes < 0 || plane0 > k->nplanes - nplanes) return fail(PG_EINVAL, "plane range out of bounds");
+  for (int p = plane0 + 1; p < plane0 + nplanes; ++p)
+    if (k->support[p] != k->support[plane0]) return fail(PG_EINVAL, "planes of one transfer must share their support");
+  return PG_OK;
+}
+}  // namespace
+
+int pg_kernels_export(const pg_kernels* k, int32_t plane0, int32_t nplanes, float* dst, void* stream) {
+  pg::set_error("");
+  if (!k || (!dst && nplanes > 0)) return fail(PG_EINVAL, "kernels and dst must be non-NULL");
+  const int rc = check_plane_range(k, plane0, nplanes);
+  if (rc != PG_OK || nplanes == 0) return rc;
+  const int nqc = k->npol * k->npol;
+  pg::CellScale one;
+  for (float& v : one.v) v = 1.0f;
+  PGM_HIP(pg::cell_io(k->table.p, k->storage, nqc, pg::chunk_entries(k->storage, nqc), k->os, k->support[plane0],
+                      k->plane_offset[plane0], nplanes, 0, nqc, dst, false, one, static_cast<hipStream_t>(stream)),
+          "export cells");
+  return PG_OK;
+}
+
+int pg_kernels_import(pg_kernels* k, int32_t plane0, int32_t nplanes, const float* src, const float* cell_scale,
+                      void* stream) {
+  pg::set_error("");
+  if (!k || (!src && nplanes > 0)) return fail(PG_EINVAL, "kernels and src must be non-NULL");
+  const int rc = check_plane_range(k, plane0, nplanes);
+  if (rc != PG_OK || nplanes == 0) return rc;
+  const int nqc = k->npol * k->npol;
+  pg::CellScale sc;
+  for (int i = 0; i < 16; ++i) sc.v[i] = (cell_scale && i < nqc) ? cell_scale[i] : 1.0f;
+  for (int i = 0; i < nqc; ++i)
+    if (!std::isfinite(sc.v[i])) return fail(PG_EINVAL, "cell_scale must be finite");
+  PGM_HIP(pg::cell_io(k->table.p, k->storage, nqc, pg::chunk_entries(k->storage, nqc), k->os, k->support[plane0],
+                      k->plane_offset[plane0], nplanes, 0, nqc, const_cast<float*>(src), true, sc,
+                      static_cast<hipStream_t>(stream)),
+          "import cells");
   return PG_OK;
 }
 

@@ -6,9 +6,12 @@
 // U = i (XY + YX)/2 on request).  Gridding screens are (M'^S)^-1 S, where M' has
 // its diagonal regularised by Eq. 6 (Sec. 3.3); degridding screens are
 // (S^-1 M^S)^H, whose conjugate carries the Stokes sky to observed correlations.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "common.hpp"
@@ -17,6 +20,24 @@ namespace pg {
 namespace {
 
 using cd = std::complex<double>;
+
+// Runs fn(begin, end) over [0, n) split across host threads (per-pixel work is independent).
+template <class F>
+void parallel_for(size_t n, F fn) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nt = std::min<size_t>({hw, 16, std::max<size_t>(1, n / 4096)});
+  if (nt <= 1) {
+    fn(size_t{0}, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const size_t step = (n + nt - 1) / nt;
+  for (size_t t = 0; t < nt; ++t) {
+    const size_t b = t * step, e = std::min(n, b + step);
+    if (b < e) th.emplace_back(fn, b, e);
+  }
+  for (auto& x : th) x.join();
+}
 
 struct M4 {
   cd a[4][4];
@@ -100,7 +121,8 @@ bool build_screens(int npol, int kind, const double* jones, int mk, double eps, 
   }
   // M^S at every lattice sample.
   std::vector<M4> ms(npix);
-  for (size_t px = 0; px < npix; ++px) {
+  parallel_for(npix, [&](size_t px0, size_t px1) {
+  for (size_t px = px0; px < px1; ++px) {
     cd j[2][2];
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
@@ -118,6 +140,7 @@ bool build_screens(int npol, int kind, const double* jones, int mk, double eps, 
           for (int d = 0; d < 2; ++d) m.a[2 * a + b][2 * c + d] = j[a][c] * std::conj(j[b][d]);
     ms[px] = mul(mul(s, m), sinv);
   }
+  });
   phi.assign(2 * 16 * npix, 0.0);
   if (kind == PG_KIND_GRID) {
     double beta[4];
@@ -126,7 +149,9 @@ bool build_screens(int npol, int kind, const double* jones, int mk, double eps, 
       for (size_t px = 0; px < npix; ++px) mx = std::max(mx, std::abs(ms[px].a[p][p]));
       beta[p] = (eps / 2.0) * mx * (eps / 2.0) * mx;
     }
-    for (size_t px = 0; px < npix; ++px) {
+    std::atomic<bool> singular{false};
+    parallel_for(npix, [&](size_t px0, size_t px1) {
+    for (size_t px = px0; px < px1; ++px) {
       M4 reg = ms[px];
       for (int p = 0; p < 4; ++p) {  // Eq. 6 on a copy of the diagonal
         cd b = reg.a[p][p];
@@ -136,8 +161,8 @@ bool build_screens(int npol, int kind, const double* jones, int mk, double eps, 
       }
       M4 inv;
       if (!inverse(reg, inv)) {
-        err = "regularised Stokes Mueller matrix is singular at a lattice sample";
-        return false;
+        singular = true;
+        continue;
       }
       M4 f = mul(inv, s);
       for (int q = 0; q < 4; ++q)
@@ -147,8 +172,14 @@ bool build_screens(int npol, int kind, const double* jones, int mk, double eps, 
           phi[o + 1] = f.a[q][c].imag();
         }
     }
+    });
+    if (singular) {
+      err = "regularised Stokes Mueller matrix is singular at a lattice sample";
+      return false;
+    }
   } else {
-    for (size_t px = 0; px < npix; ++px) {
+    parallel_for(npix, [&](size_t px0, size_t px1) {
+    for (size_t px = px0; px < px1; ++px) {
       M4 a = mul(sinv, ms[px]);
       for (int q = 0; q < 4; ++q)
         for (int c = 0; c < 4; ++c) {
@@ -158,6 +189,7 @@ bool build_screens(int npol, int kind, const double* jones, int mk, double eps, 
           phi[o + 1] = v.imag();
         }
     }
+    });
   }
   return true;
 }

@@ -64,7 +64,7 @@ EXPORTS = {
     "pg_plan_info": (c_int, [c_void_p, POINTER(PgPlanDesc)]),
     "pg_plan_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pg_plan_destroy": (None, [c_void_p]),
-    "pg_plan_set_launch": (c_int, [c_void_p, c_int32, c_int32, c_int32]),
+    "pg_plan_set_launch": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
     "pg_grid": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "pg_degrid": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "pg_taper": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]),
@@ -74,6 +74,9 @@ EXPORTS = {
     "pg_batch_work_items": (c_int64, [c_void_p]),
     "pg_batch_destroy": (None, [c_void_p]),
     "pg_kernels_write_cell": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "pg_kernels_alloc": (c_int, [POINTER(PgKernelSpec), c_void_p, POINTER(c_void_p)]),
+    "pg_kernels_export": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+    "pg_kernels_import": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "pg_mlp_create": (c_int, [c_int32, c_int32, c_int32, c_int64, c_int32, ctypes.c_uint64, c_void_p,
                               POINTER(c_void_p)]),
     "pg_mlp_forward": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
@@ -125,30 +128,32 @@ def _ptr(t):
     return c_void_p(0 if t is None else t.data_ptr())
 
 
-_alloc_refs = []
+# The callback pair handed to the library.  Every device buffer keeps the function pointers it was
+# allocated with and frees through them, so the pair is created once and never released.
+_torch_hooks = None
 
 
 def use_torch_allocator(enable: bool = True):
-    """Route the library's device allocations through torch's caching allocator."""
+    """Route the library's device allocations through torch's caching allocator (idempotent);
+    enable=False returns new allocations to hipMalloc (buffers already made still free through torch)."""
+    global _torch_hooks
     import torch
 
     if not enable:
         lib().pg_set_allocator(ALLOC_FN(), FREE_FN(), None)
-        _alloc_refs.clear()
         return
+    if _torch_hooks is None:
+        def _alloc(size, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(size), stream=int(stream or 0))
+            except Exception:
+                return None
 
-    def _alloc(size, stream, ctx):
-        try:
-            return torch.cuda.caching_allocator_alloc(int(size), stream=int(stream or 0))
-        except Exception:
-            return None
+        def _free(ptr, stream, ctx):
+            torch.cuda.caching_allocator_delete(int(ptr))
 
-    def _free(ptr, stream, ctx):
-        torch.cuda.caching_allocator_delete(int(ptr))
-
-    a, f = ALLOC_FN(_alloc), FREE_FN(_free)
-    _alloc_refs[:] = [a, f]
-    lib().pg_set_allocator(a, f, None)
+        _torch_hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+    lib().pg_set_allocator(_torch_hooks[0], _torch_hooks[1], None)
 
 
 def _geometry_struct(geom):
@@ -197,6 +202,33 @@ class Kernels:
         """Overwrite cell (q, c) of `plane` from device float [os][os][S][S][2]."""
         _check(lib().pg_kernels_write_cell(self._h, int(plane), int(q), int(c), _ptr(src), _stream(stream)))
 
+    def export_planes(self, plane0: int, nplanes: int, out=None, stream=None):
+        """Cells of planes plane0.. (one support S) as float32 [nplanes][npol][npol][os][os][S][S][2]."""
+        import torch
+
+        s = int(self.geom.support[plane0])
+        shape = (nplanes, self.npol, self.npol, self.os, self.os, s, s, 2)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device="cuda")
+        elif out.numel() < int(np.prod(shape)) or not out.is_contiguous() or out.dtype != torch.float32:
+            raise ValueError("out must be a contiguous float32 tensor of at least the export size")
+        _check(lib().pg_kernels_export(self._h, int(plane0), int(nplanes), _ptr(out), _stream(stream)))
+        return out.view(-1)[:int(np.prod(shape))].view(shape)
+
+    def import_planes(self, plane0: int, nplanes: int, src, cell_scale=None, stream=None):
+        """Overwrite every cell of planes plane0.. with cell_scale[q npol + c] * src (layout of export_planes)."""
+        s = int(self.geom.support[plane0])
+        need = nplanes * self.npol ** 2 * self.os ** 2 * s * s * 2
+        if src.numel() < need or not src.is_contiguous() or str(src.dtype) != "torch.float32":
+            raise ValueError("src must be a contiguous float32 tensor of at least the import size")
+        sp = None
+        if cell_scale is not None:
+            sc = np.ascontiguousarray(cell_scale, dtype=np.float32)
+            if sc.size != self.npol ** 2:
+                raise ValueError("cell_scale needs npol^2 values")
+            sp = sc.ctypes.data_as(c_void_p)
+        _check(lib().pg_kernels_import(self._h, int(plane0), int(nplanes), _ptr(src), sp, _stream(stream)))
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.pg_kernels_destroy(self._h)
@@ -216,6 +248,15 @@ def make_kernels(geom, npol: int, kind: int = KIND_GRID, jones=None, eps_null: f
     spec = PgKernelSpec(g, int(npol), int(kind), jp, float(eps_null), int(convention), int(storage))
     h = c_void_p()
     _check(lib().pg_make_kernels(ctypes.byref(spec), _stream(stream), ctypes.byref(h)))
+    return Kernels(h, geom)
+
+
+def kernels_alloc(geom, npol: int, kind: int = KIND_GRID, storage: int = STORE_F32, stream=None) -> Kernels:
+    """A kernel set of this geometry whose table is zero, to be filled with Kernels.import_planes."""
+    g, keep = _geometry_struct(geom)
+    spec = PgKernelSpec(g, int(npol), int(kind), None, 0.0, STOKES_IAU, int(storage))
+    h = c_void_p()
+    _check(lib().pg_kernels_alloc(ctypes.byref(spec), _stream(stream), ctypes.byref(h)))
     return Kernels(h, geom)
 
 
@@ -242,9 +283,11 @@ class Plan:
         _check(lib().pg_plan_copy(self._h, _ptr(perm), _ptr(fine), _ptr(items), _stream()))
         return perm[:self.nvis], fine[:self.n_kept], items[:self.n_items]
 
-    def set_launch(self, grid_variant: int = 0, grid_waves: int = 16, degrid_waves: int = 16):
-        """Launch tuning (grid variant 0 auto / 1 atomic / 2 banded, waves per workgroup)."""
-        _check(lib().pg_plan_set_launch(self._h, int(grid_variant), int(grid_waves), int(degrid_waves)))
+    def set_launch(self, grid_variant: int = 0, grid_waves: int = 16, degrid_waves: int = 16, xcd_group: int = 1):
+        """Launch tuning (grid variant 0 auto / 1 atomic / 2 banded, waves per workgroup, consecutive
+        work items per XCD)."""
+        _check(lib().pg_plan_set_launch(self._h, int(grid_variant), int(grid_waves), int(degrid_waves),
+                                        int(xcd_group)))
         return self
 
     def __del__(self):

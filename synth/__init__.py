@@ -320,3 +320,80 @@ def config3(seed: int = SEED_BASE + 3, nfields: int = 16, n: int = 4096, cell: f
         out.append(Workload(f"c3-field{i:02d}-{nu / 1e6:.0f}MHz", geom, uvw, 4, beam=beam,
                             extra={"freq_hz": nu}))
     return out
+
+
+# --------------------------------------------------------------------------- c4: kernel surrogate
+
+@dataclass
+class RotatedLeakageBeam:
+    """The leakage beam of an alt-az antenna seen at parallactic angle pa.
+
+    The pattern turns with pa on the sky and the X/Y feed basis turns with it:
+    J(l, m) = J0(l cos pa + m sin pa, -l sin pa + m cos pa) R(pa), R(pa) = [[cos, -sin], [sin, cos]].
+    """
+
+    base: GaussianLeakageBeam
+    pa: float
+
+    def jones(self, l, m) -> np.ndarray:
+        l = np.asarray(l, dtype=np.float64)
+        m = np.asarray(m, dtype=np.float64)
+        c, s = math.cos(self.pa), math.sin(self.pa)
+        j = self.base.jones(c * l + s * m, -s * l + c * m)
+        rot = np.array([[c, -s], [s, c]], dtype=np.complex128)
+        return j @ rot
+
+
+@dataclass
+class SurrogateSetup:
+    """Kernel-surrogate workload (c4).
+
+    Kernels: 48 x 48 taps x 8 x 8 phases on the config-1 grid (256^2, field of view 0.1 rad),
+    lattice mk = 256, for w in [-w_max, w_max], frequency in [nu_lo, nu_hi] (power-beam FWHM
+    1 deg x 1.4 GHz / nu) and parallactic angle in [-pi, pi]; one leakage pattern (seeded) for all.
+    Evaluation: the config-1 uv coverage and point sources, full polarisation, at (nu_eval, pa_eval).
+    """
+
+    geom: Geometry                 # 8 linear planes on [-w_max, w_max]: the nearest-plane baseline
+    leakage: GaussianLeakageBeam   # theta is replaced per frequency
+    w_max: float
+    nu_lo: float
+    nu_hi: float
+    nu_eval: float
+    pa_eval: float
+    uvw: np.ndarray
+    src_l: np.ndarray
+    src_m: np.ndarray
+    src_iquv: np.ndarray
+
+    def beam(self, nu: float, pa: float) -> RotatedLeakageBeam:
+        b = GaussianLeakageBeam(theta=1.0 * DEG * 1.4e9 / nu, dxy=self.leakage.dxy, dyx=self.leakage.dyx,
+                                level=self.leakage.level)
+        return RotatedLeakageBeam(b, pa)
+
+    def plane_geometry(self, w_planes) -> Geometry:
+        """The same grid and kernels with another (ascending) w-plane set."""
+        p = len(w_planes)
+        return Geometry(n=self.geom.n, cell=self.geom.cell, os=self.geom.os, w_planes=np.asarray(w_planes),
+                        support=np.full(p, int(self.geom.support[0]), np.int32),
+                        tile=np.full(p, int(self.geom.tile[0]), np.int32), aa_support=self.geom.aa_support,
+                        mk=self.geom.mk)
+
+    def draw(self, count: int, rng):
+        """count seeded (w, nu, pa) draws: w ~ U(-w_max, w_max), nu ~ U(nu_lo, nu_hi), pa ~ U(-pi, pi)."""
+        return (rng.uniform(-self.w_max, self.w_max, count), rng.uniform(self.nu_lo, self.nu_hi, count),
+                rng.uniform(-math.pi, math.pi, count))
+
+
+def config4(seed: int = SEED_BASE + 4, nvis: int = 20000) -> SurrogateSetup:
+    rng = np.random.default_rng(seed)
+    c1 = config1(nvis=nvis)
+    n, cell, support = 256, 0.1 / 256, 48
+    planes = linear_w_planes(8, 200.0)
+    geom = Geometry(n=n, cell=cell, os=8, w_planes=planes, support=np.full(8, support, np.int32),
+                    tile=default_tiles(np.full(8, support, np.int32), 4), aa_support=7, mk=256)
+    leak = seeded_leakage_beam(1.0 * DEG, rng)
+    iquv = np.zeros((len(c1.src_l), 4))
+    iquv[:, 0] = c1.src_iquv[:, 0]
+    return SurrogateSetup(geom=geom, leakage=leak, w_max=200.0, nu_lo=700e6, nu_hi=1800e6, nu_eval=700e6,
+                          pa_eval=0.4, uvw=c1.uvw, src_l=c1.src_l, src_m=c1.src_m, src_iquv=iquv)

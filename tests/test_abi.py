@@ -105,6 +105,10 @@ def test_null_handles_are_rejected():
     assert lib.pg_plan_info(None, None) == pg.EINVAL
     assert lib.pg_plan_copy(None, None, None, None, None) == pg.EINVAL
     assert lib.pg_kernels_copy_table(None, None, None) == pg.EINVAL
+    assert lib.pg_plan_set_launch(None, 0, 16, 16, 1) == pg.EINVAL
+    assert lib.pg_kernels_alloc(None, None, ctypes.byref(h)) == pg.EINVAL
+    assert lib.pg_kernels_export(None, 0, 1, None, None) == pg.EINVAL
+    assert lib.pg_kernels_import(None, 0, 1, None, None, None) == pg.EINVAL
     lib.pg_kernels_destroy(None)
     lib.pg_plan_destroy(None)
     assert "non-NULL" in lib.pg_last_error().decode()
@@ -124,3 +128,15 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pg, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         pg.lib()
+
+
+def test_torch_allocator_hooks_are_created_once():
+    """Objects free through the hooks they were allocated with, so re-enabling the torch allocator
+    must hand the library the same callback objects (a fresh pair would free the old ones)."""
+    pytest.importorskip("torch")
+    pg.use_torch_allocator(True)
+    first = pg._torch_hooks
+    pg.use_torch_allocator(False)
+    pg.use_torch_allocator(True)
+    assert pg._torch_hooks is first and first is not None
+    pg.use_torch_allocator(False)

@@ -31,13 +31,14 @@ def full():
     from paper_2206_15117_amd import autotune
 
     w = synth.config2()
-    g, chunk, _, gw, dw = autotune.apply(w.geom, 4, pg.STORE_F32)
+    launch = autotune.apply(w.geom, 4, pg.STORE_F32)
+    g = launch.geom
     w.geom = g
     jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
     kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=w.eps_null)
     kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones)
     uvw = torch.from_numpy(w.uvw).cuda()
-    p = pg.plan(kg, uvw, max_chunk=chunk).set_launch(0, gw, dw)
+    p = autotune.plan(kg, uvw, launch)
     loc = geometry.locate(g, w.uvw)
     counts = np.bincount(loc["plane"], minlength=g.nplanes)
     dense = int(np.argmax(counts))
@@ -51,7 +52,8 @@ def full():
     td = kernels.make_tables(g, mueller.phi_degrid(jones), planes=planes)
     n = g.n
     sign = ((-1.0) ** (np.arange(n)[:, None] + np.arange(n)[None, :]))[None]
-    return dict(w=w, kg=kg, kd=kd, uvw=uvw, p=p, sample=np.sort(sample), tg=tg, td=td, sign=sign, chunk=chunk)
+    return dict(w=w, kg=kg, kd=kd, uvw=uvw, p=p, sample=np.sort(sample), tg=tg, td=td, sign=sign,
+                chunk=launch.max_chunk)
 
 
 def test_full_plan_bit_exact(full):

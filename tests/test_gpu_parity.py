@@ -200,17 +200,22 @@ def test_c2_grid_parity(c2_case, max_chunk, variant):
         assert rel(got[q], want[q]) < TOL, q
 
 
-@pytest.mark.parametrize("waves", [4, 8, 16])
-def test_c2_launch_shapes(c2_case, waves):
-    """Every waves-per-workgroup setting of the banded grid and the degrid gives the oracle result."""
+@pytest.mark.parametrize("waves,group", [(4, 1), (8, 1), (16, 1), (8, 3), (16, 64), (4, 4096)])
+def test_c2_launch_shapes(c2_case, waves, group):
+    """Every waves-per-workgroup setting of the banded grid and the degrid, and XCD item groupings
+    with a padded tail (items not a multiple of 8 x group), give the oracle result."""
     w, vis, tg, td, kg, kd = c2_case
     rng = np.random.default_rng(40 + waves)
     g = (rng.standard_normal((4, 256, 256)) + 1j * rng.standard_normal((4, 256, 256))).astype(np.complex64)
-    p = pg.plan(kg, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves)
+    p = pg.plan(kg, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves, group)
+    assert group != 4096 or p.n_items % (8 * group) != 0
     got = host(pg.grid(p, kg, dev(vis)))
     want = gridding.grid(w.geom, tg, w.uvw, vis)
     assert rel(got, want) < TOL
-    pd = pg.plan(kd, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves)
+    if group > 1:
+        got_a = host(pg.grid(p.set_launch(1, waves, waves, group), kg, dev(vis)))
+        assert rel(got_a, want) < TOL
+    pd = pg.plan(kd, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves, group)
     gv = host(pg.degrid(pd, kd, dev(g)))
     assert rel(gv, gridding.degrid(w.geom, td, w.uvw, g)) < TOL
 
