@@ -48,6 +48,11 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    """Progress of the benchmark's own steps, on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in ("grid.hip", "common.hpp"):
@@ -159,6 +164,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    log(f"full-pol step timed: {1e3 * wall / args.steps:.2f} ms")
 
     # algorithmic work of one grid (or degrid) launch: 8 flops per complex MAC, 16 Mueller
     # cells per tap, S_p^2 taps for every kept visibility (plane of each work item)
@@ -196,9 +202,11 @@ def main():
         del grid_buf, fft_buf, img, vis_out
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(max(2, args.steps // 2), 1)
+        log(f"batched step timed: {out['batched']['ms_per_step']:.1f} ms")
     if not args.no_surrogate:
         torch.cuda.empty_cache()
         out["surrogate"] = bench_surrogate(args.surrogate_kernels)
+        log("learned-kernel section done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -229,7 +237,7 @@ def bench_batched(steps, warmup):
         kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones, storage=pg.STORE_F16)
         uvw = torch.from_numpy(w.uvw).cuda()
         ks.append((kg, kd))
-        ps.append((autotune.plan(kg, uvw, launch), autotune.plan(kd, uvw, launch)))
+        ps.append(autotune.batch_plans(kg, kd, uvw, launch))
         vis.append(torch.from_numpy(synth.random_vis(w.nvis, 4, rng)).cuda())
         outs.append(torch.empty((w.nvis, 4), dtype=torch.complex64, device="cuda"))
     torch.cuda.synchronize()
@@ -316,9 +324,9 @@ def bench_surrogate(n_kernels):
     planes = 8
     teacher = sg.Teacher(s, synth.jones_on_lattice, planes=planes, seed=1)
     calls = -(-n_kernels // (planes * sg.N_CELLS))
-    x, c, basis, info = sg.teacher_data(teacher, scale, calls, basis_calls=32, rank=256)
+    x, c, basis, info = sg.teacher_data(teacher, scale, calls, basis_calls=32, rank=256, log=log)
     t0 = time.perf_counter()
-    net_r, losses = sg.train_coefficients(x, c, steps=20000, batch=2048, lr=5e-3)
+    net_r, losses = sg.train_coefficients(x, c, steps=20000, batch=2048, lr=5e-3, log=log)
     net = sg.fold(net_r, basis)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
@@ -414,13 +422,18 @@ def cpu_baseline(w, nsample):
 
     planes = sorted(set(nearest_plane(uvw[:, 2], w.geom.w_planes).tolist()))
     jones = synth.jones_on_lattice(w.beam, w.geom.mk, w.geom.fov)
-    tabs = kernels.make_tables(w.geom, mueller.phi_grid(jones, w.eps_null), planes=planes)
+    phi = mueller.phi_grid(jones, w.eps_null)
+    tabs = [None] * w.geom.nplanes
+    for i, pl in enumerate(planes):
+        tabs[pl] = kernels.make_tables(w.geom, phi, planes=[pl])[pl]
+        log(f"oracle table {i + 1}/{len(planes)} built")
     vis = synth.random_vis(nsample, 4, rng)
     from threadpoolctl import threadpool_limits
 
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         g = gridding.grid(w.geom, tabs, uvw, vis)
+        log("oracle grid done")
         gridding.degrid(w.geom, tabs, uvw, g)
         dt = time.perf_counter() - t0
     return {"value": nsample / dt, "unit": "vis/s", "cores": 1, "kind": "oracle",

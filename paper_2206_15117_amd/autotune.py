@@ -18,7 +18,8 @@ from collections import namedtuple
 
 import numpy as np
 
-Launch = namedtuple("Launch", "geom max_chunk variant grid_waves degrid_waves xcd_group")
+Launch = namedtuple("Launch", "geom max_chunk variant grid_waves degrid_waves xcd_group batch_grid_waves "
+                               "batch_degrid_waves")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
@@ -85,11 +86,25 @@ def apply(geom, npol, storage) -> Launch:
     cfg = tuned_config(npol, storage, geom.os, geom.support)
     g = copy.copy(geom)
     if cfg is None:
-        return Launch(g, 1024, 0, 16, 16, 1)
+        return Launch(g, 1024, 0, 16, 16, 1, 16, 16)
     g.tile = np.asarray(cfg["grid"]["tiles"], dtype=np.int32)
     same = cfg["grid"]["wgs_per_cu"] == cfg["degrid"]["wgs_per_cu"]
-    return Launch(g, int(cfg["grid"]["max_chunk"]), int(cfg["grid"].get("variant", 2)), int(cfg["grid"]["waves"]),
-                  int(cfg["degrid"]["waves"]) if same else 16, int(cfg.get("xcd_group", 1)))
+    gw, dw = int(cfg["grid"]["waves"]), int(cfg["degrid"]["waves"]) if same else 16
+    batch = cfg.get("batch", {})
+    return Launch(g, int(cfg["grid"]["max_chunk"]), int(cfg["grid"].get("variant", 2)), gw, dw,
+                  int(cfg.get("xcd_group", 1)), int(batch.get("grid_waves", gw)), int(batch.get("degrid_waves", dw)))
+
+
+def batch_plans(kernels_grid, kernels_degrid, uvw, launch: Launch):
+    """(grid plan, degrid plan) for one field of a batched launch, with the persistent kernels'
+    waves per workgroup (a batch takes its launch shape from its first field's plan)."""
+    from . import polgrid as pg
+
+    pg_ = pg.plan(kernels_grid, uvw, max_chunk=launch.max_chunk)
+    pd_ = pg.plan(kernels_degrid, uvw, max_chunk=launch.max_chunk)
+    pg_.set_launch(0, launch.batch_grid_waves, launch.degrid_waves, launch.xcd_group)
+    pd_.set_launch(0, launch.grid_waves, launch.batch_degrid_waves, launch.xcd_group)
+    return pg_, pd_
 
 
 def plan(kernels, uvw, launch: Launch):
@@ -198,6 +213,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2"])
     ap.add_argument("--storage", type=int, default=0)
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
+    ap.add_argument("--wgs", default="1,2,3,4", help="workgroups per CU to try")
+    ap.add_argument("--waves", default="4,8,16", help="waves per workgroup to try")
+    ap.add_argument("--chunks", default="256,1024", help="work item lengths to try")
     ap.add_argument("--save", action="store_true")
     args = ap.parse_args()
     from . import polgrid as pg
@@ -209,7 +227,9 @@ def main():
     jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
     uvw = torch.from_numpy(w.uvw).cuda()
     vis = torch.from_numpy(synth.random_vis(w.nvis, 4, np.random.default_rng(3))).cuda()
-    kw = dict(wgs=(1, 2, 4), waves=(4, 16), chunks=(256,)) if args.quick else {}
+    ints = lambda t: tuple(int(v) for v in t.split(","))
+    kw = dict(wgs=(1, 2, 4), waves=(4, 16), chunks=(256,)) if args.quick else dict(
+        wgs=ints(args.wgs), waves=ints(args.waves), chunks=ints(args.chunks))
     best, results = tune(g, 4, jones, uvw, vis, w.eps_null, storage=args.storage, **kw)
     print("BEST", json.dumps(best), flush=True)
     if args.save:

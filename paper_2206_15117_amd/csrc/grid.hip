@@ -48,17 +48,16 @@ template <int NQC, typename TapT>
 struct TapChunks {
   static constexpr int E = NQC < Chunk<TapT>::E ? NQC : Chunk<TapT>::E;
   static constexpr int NCH = NQC / E;
-  const TapT* base[NCH];  // wave-uniform: chunk j of one phase block [chunk][SS][E]
-  __device__ TapChunks(const TapT* ph, int ss) {
-#pragma unroll
-    for (int j = 0; j < NCH; ++j) base[j] = ph + static_cast<size_t>(j) * ss * E;
-  }
-  // All npol^2 taps of tap index t (a per-lane 32-bit offset from uniform chunk bases).
+  const TapT* base;     // wave-uniform: chunk 0 of one phase block [chunk][SS][E]
+  uint32_t chunk_bytes;  // distance between chunks, SS * E * sizeof(TapT)
+  __device__ TapChunks(const TapT* ph, int ss)
+      : base(ph), chunk_bytes(static_cast<uint32_t>(ss) * E * static_cast<uint32_t>(sizeof(TapT))) {}
+  // All npol^2 taps of tap index t: one scalar base plus a 32-bit per-lane offset per chunk.
   __device__ void load(uint32_t t, float2 (&out)[NQC]) const {
-    const uint32_t boff = t * static_cast<uint32_t>(E * sizeof(TapT));  // 32-bit lane offset
+    const uint32_t boff = t * static_cast<uint32_t>(E * sizeof(TapT));
 #pragma unroll
     for (int j = 0; j < NCH; ++j) {
-      const TapT* p = reinterpret_cast<const TapT*>(reinterpret_cast<const char*>(base[j]) + boff);
+      const TapT* p = reinterpret_cast<const TapT*>(reinterpret_cast<const char*>(base) + boff + j * chunk_bytes);
       if constexpr (E == 2) {
         const float4 v = *reinterpret_cast<const float4*>(p);
         out[2 * j] = make_float2(v.x, v.y);
@@ -166,11 +165,64 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(const Item* __restrict__
   }
 }
 
+// One row (visibility) of a work item as one wave of the banded gridder sees it: the footprint rows
+// inside the wave's band [r0, r1), flattened to cnt = (b - a) S taps starting at tap t0, with the
+// row's visibility and kernel phase made wave-uniform (readlane of the lane that fetched them).
+// j < 0 gives an empty row.
+template <int NP, typename TapT>
+struct BandRow {
+  int cnt = 0, a = 0, lx = 0;
+  uint32_t t0 = 0;
+  float2 v[NP];
+  TapChunks<NP * NP, TapT> tc;
+  __device__ BandRow(int j, int m_ly, int m_lx, int m_ph, int m_k, const float2* __restrict__ vis, int r0, int r1,
+                     int S, int SS, const TapT* plane_table)
+      : tc(plane_table, SS) {
+    if (j < 0) {
+#pragma unroll
+      for (int c = 0; c < NP; ++c) v[c] = make_float2(0.0f, 0.0f);
+      return;
+    }
+    const int ly = __builtin_amdgcn_readlane(m_ly, j);
+    a = max(ly, r0);
+    cnt = (min(ly + S, r1) - a) * S;
+    t0 = static_cast<uint32_t>((a - ly) * S);
+    lx = __builtin_amdgcn_readlane(m_lx, j);
+    const int ph = __builtin_amdgcn_readlane(m_ph, j);
+    tc = TapChunks<NP * NP, TapT>(plane_table + static_cast<size_t>(ph) * SS * NP * NP, SS);
+    const int k = __builtin_amdgcn_readlane(m_k, j);  // uniform: the row's values come in by scalar loads
+#pragma unroll
+    for (int c = 0; c < NP; ++c) v[c] = vis[static_cast<size_t>(k) * NP + c];
+  }
+  // Adds the Mueller product of tap u (0 <= u < cnt) into the LDS sub-grid: all npol reads are
+  // issued before the arithmetic and all writes after it.
+  __device__ __forceinline__ void apply(float2* lds, int u, const float2 (&tap)[NP * NP], float inv_s, int S, int P,
+                                        int WP) const {
+    const int rr = static_cast<int>((static_cast<float>(u) + 0.5f) * inv_s);
+    const int tx = u - rr * S;
+    const int off = (a + rr) * P + lx + tx;
+    float2 g[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) g[q] = lds[q * WP + off];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        const float2 t2 = tap[q * NP + c];
+        g[q].x = fmaf(t2.x, v[c].x, fmaf(-t2.y, v[c].y, g[q].x));
+        g[q].y = fmaf(t2.x, v[c].y, fmaf(t2.y, v[c].x, g[q].y));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) lds[q * WP + off] = g[q];
+  }
+};
+
 // Banded variant: the sub-grid rows are split into NW contiguous bands of equal load (rows
 // weighted by how many footprints of the item cover them); wave w owns band w and walks every
 // visibility of the item, taking only the footprint rows inside its band.  Bands are disjoint, so
 // the sub-grid (complex [q][W][P] in LDS) is updated with plain read-modify-write, no LDS atomics.
-template <int NP, typename TapT, int NW>
+template <int NP, typename TapT, int NW, bool PAIR>
 __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __restrict__ fine,
                                                  const int32_t* __restrict__ perm, const float2* __restrict__ vis,
                                                  const TapT* __restrict__ table, const PlaneInfo* __restrict__ planes,
@@ -241,7 +293,7 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
   // readlane, so walking the item costs one memory latency per 64 rows, not two per row.
   for (int blk = it.start; blk < it.end && r0 < r1; blk += 64) {
     const int mine = blk + lane;
-    int m_ly = -1 << 20, m_lx = 0, m_ph = 0, m_k = 0;
+    int m_ly = -(1 << 20), m_lx = 0, m_ph = 0, m_k = 0;
     if (mine < it.end) {
       const int2 f = fine[mine];
       const int x0 = ceil_div_i(f.x - half + 1, os), y0 = ceil_div_i(f.y - half + 1, os);
@@ -250,43 +302,51 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
       m_ph = (y0 * os - f.y + half - 1) * os + (x0 * os - f.x + half - 1);
       m_k = perm[mine];
     }
-    float2 m_v[NP];
-#pragma unroll
-    for (int c = 0; c < NP; ++c)
-      m_v[c] = (mine < it.end) ? vis[static_cast<size_t>(m_k) * NP + c] : make_float2(0.0f, 0.0f);
     const int nrow = min(64, it.end - blk);
-    for (int j = 0; j < nrow; ++j) {
-      const int ly = __builtin_amdgcn_readlane(m_ly, j);
-      const int a = max(ly, r0), b = min(ly + S, r1);
-      if (a >= b) continue;
-      const int lx = __builtin_amdgcn_readlane(m_lx, j);
-      const int ph = __builtin_amdgcn_readlane(m_ph, j);
-      float2 v[NP];
-#pragma unroll
-      for (int c = 0; c < NP; ++c)
-        v[c] = make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_v[c].x), j)),
-                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_v[c].y), j)));
-      const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(ph) * SS * NP * NP, SS);
-      const int cnt = (b - a) * S;
-      const uint32_t t0 = static_cast<uint32_t>((a - ly) * S);
-#pragma unroll 2
-      for (int u = lane; u < cnt; u += 64) {
-        const int rr = static_cast<int>((static_cast<float>(u) + 0.5f) * inv_s);
-        const int tx = u - rr * S;
-        float2 tap[NP * NP];
-        tc.load(t0 + static_cast<uint32_t>(u), tap);
-        const int off = (a + rr) * P + lx + tx;
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          float2 g = lds[q * WP + off];
-#pragma unroll
-          for (int c = 0; c < NP; ++c) {
-            const float2 t2 = tap[q * NP + c];
-            g.x = fmaf(t2.x, v[c].x, fmaf(-t2.y, v[c].y, g.x));
-            g.y = fmaf(t2.x, v[c].y, fmaf(t2.y, v[c].x, g.y));
-          }
-          lds[q * WP + off] = g;
+    // With PAIR, rows are taken two at a time: the first 64 taps of both are requested before either
+    // is applied, so one memory latency covers two rows.  LDS updates stay in row order (a wave's LDS
+    // operations execute in program order), so overlapping footprints need no synchronisation.
+    int j = 0;
+    for (;;) {
+      int ja = -1, jb = -1;
+      for (; j < nrow; ++j) {
+        const int ly = __builtin_amdgcn_readlane(m_ly, j);
+        if (max(ly, r0) < min(ly + S, r1)) {
+          ja = j++;
+          break;
         }
+      }
+      ja = __builtin_amdgcn_readfirstlane(ja);  // row indices are wave-uniform: keep them scalar
+      if (ja < 0) break;
+      if constexpr (PAIR) {
+        for (; j < nrow; ++j) {
+          const int ly = __builtin_amdgcn_readlane(m_ly, j);
+          if (max(ly, r0) < min(ly + S, r1)) {
+            jb = j++;
+            break;
+          }
+        }
+        jb = __builtin_amdgcn_readfirstlane(jb);
+      }
+      const BandRow<NP, TapT> ra(ja, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset);
+      const BandRow<NP, TapT> rb(jb, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset);
+      float2 ta[NP * NP], tb[NP * NP];
+      const bool la = lane < ra.cnt, lb = lane < rb.cnt;
+      if (la) ra.tc.load(ra.t0 + static_cast<uint32_t>(lane), ta);
+      if (lb) rb.tc.load(rb.t0 + static_cast<uint32_t>(lane), tb);
+      if (la) ra.apply(lds, lane, ta, inv_s, S, P, WP);
+#pragma unroll 1
+      for (int u = lane + 64; u < ra.cnt; u += 64) {
+        float2 t[NP * NP];
+        ra.tc.load(ra.t0 + static_cast<uint32_t>(u), t);
+        ra.apply(lds, u, t, inv_s, S, P, WP);
+      }
+      if (lb) rb.apply(lds, lane, tb, inv_s, S, P, WP);
+#pragma unroll 1
+      for (int u = lane + 64; u < rb.cnt; u += 64) {
+        float2 t[NP * NP];
+        rb.tc.load(rb.t0 + static_cast<uint32_t>(u), t);
+        rb.apply(lds, u, t, inv_s, S, P, WP);
       }
     }
   }
@@ -323,7 +383,9 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_kernel(const Item* __rest
   extern __shared__ float lds_f[];
   const int item = xcd_item(blockIdx.x, group);
   if (item >= n_items) return;
-  grid_item_banded<NP, TapT, NW>(items[item], fine, perm, vis, table, planes, os, n, grid, flags, sub_bytes, lds_f);
+  // two rows in flight costs registers: 1024-thread workgroups (capped at 128) take one at a time
+  grid_item_banded<NP, TapT, NW, (NW <= 8)>(items[item], fine, perm, vis, table, planes, os, n, grid, flags,
+                                            sub_bytes, lds_f);
 }
 
 // Persistent form over many fields: each workgroup takes (field, item) pairs from a global queue
@@ -344,8 +406,10 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_persistent(const FieldArg
     if (w >= n_work) break;
     const int2 wr = work[w];
     const FieldArgs fa = fields[wr.x];
-    grid_item_banded<NP, TapT, NW>(fa.items[wr.y], fa.fine, fa.perm, fa.vis, static_cast<const TapT*>(fa.table),
-                                   fa.planes, fa.os, fa.n, fa.grid, flags, sub_bytes, lds_f);
+    // the persistent loop's own state leaves room for two rows in flight only at 4 waves per workgroup
+    grid_item_banded<NP, TapT, NW, (NW <= 4)>(fa.items[wr.y], fa.fine, fa.perm, fa.vis,
+                                              static_cast<const TapT*>(fa.table), fa.planes, fa.os, fa.n, fa.grid,
+                                              flags, sub_bytes, lds_f);
     __syncthreads();
   }
 }

@@ -198,6 +198,8 @@ def teacher_data(teacher, scale, calls: int, basis_calls: int = 64, rank: int = 
     resid = []
     for c in range(nb, calls):
         feats.append(teacher.call(buf))
+        if log is not None and (c + 1) % 256 == 0:
+            log(f"teacher call {c + 1}/{calls}")
         buf *= inv
         cc = buf @ basis.T
         coef.append(cc)
