@@ -170,7 +170,7 @@ void pg_plan_destroy(pg_plan* p);
 
 /* Launch tuning of the kernels that run over this plan (results are unchanged up to float32
  * summation order): grid_variant 0 = choose by sub-grid width, 1 = LDS-atomic accumulation,
- * 2 = row-band ownership; grid_waves and degrid_waves = waves per workgroup, 4, 8 or 16;
+ * 2 = row-band ownership; grid_waves and degrid_waves = waves per workgroup, 4, 6, 8 or 16;
  * xcd_group = how many consecutive work items (in plan order) run on one XCD, so that they share
  * its L2 (1 = plain order, up to 4096).  Set before the plan is shared between threads.
  * Errors: PG_EINVAL. */

@@ -3,7 +3,7 @@
 Searches, per geometry class (npol, storage, os, per-plane supports):
   * workgroups per CU (1-4): sets each plane's tile T to the largest sub-grid that fits
     1/k of the LDS, so every item of a launch has the same LDS footprint;
-  * waves per workgroup for grid and degrid (4, 8, 16);
+  * waves per workgroup for grid and degrid (4, 6, 8, 16);
   * the grid variant (row bands or LDS atomics) and the chunk length of work items;
   * how many consecutive work items share one XCD (and its L2), for the best shape found.
 Each candidate is timed with HIP events on a representative workload; the best choice is
@@ -129,7 +129,7 @@ def _time(fn, reps):
 
 
 def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2, 3, 4),
-         waves=(4, 8, 16), chunks=(256, 1024), verbose=True):
+         waves=(4, 6, 8, 16), chunks=(256, 1024), verbose=True):
     """Time every candidate; returns (best dict, list of all results)."""
     import copy
 
@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--storage", type=int, default=0)
     ap.add_argument("--quick", action="store_true", help="fewer candidates")
     ap.add_argument("--wgs", default="1,2,3,4", help="workgroups per CU to try")
-    ap.add_argument("--waves", default="4,8,16", help="waves per workgroup to try")
+    ap.add_argument("--waves", default="4,6,8,16", help="waves per workgroup to try")
     ap.add_argument("--chunks", default="256,1024", help="work item lengths to try")
     ap.add_argument("--save", action="store_true")
     args = ap.parse_args()

@@ -596,6 +596,7 @@ hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, fl
   if (banded) {
     switch (p->grid_waves) {
       case 4: return run_grid_banded<NP, TapT, 4>(p, k, vis, grid, flags, s);
+      case 6: return run_grid_banded<NP, TapT, 6>(p, k, vis, grid, flags, s);
       case 8: return run_grid_banded<NP, TapT, 8>(p, k, vis, grid, flags, s);
       default: return run_grid_banded<NP, TapT, 16>(p, k, vis, grid, flags, s);
     }
@@ -627,6 +628,7 @@ hipError_t run_degrid(const pg_plan* p, const pg_kernels* k, const float2* grid,
                       hipStream_t s) {
   switch (p->degrid_waves) {
     case 4: return run_degrid_nw<NP, TapT, 4>(p, k, grid, vis, flags, s);
+    case 6: return run_degrid_nw<NP, TapT, 6>(p, k, grid, vis, flags, s);
     case 8: return run_degrid_nw<NP, TapT, 8>(p, k, grid, vis, flags, s);
     default: return run_degrid_nw<NP, TapT, 16>(p, k, grid, vis, flags, s);
   }
@@ -668,10 +670,12 @@ hipError_t dispatch_batch(const pg_batch* b, int flags, hipStream_t s, bool grid
   const int nw = grid ? b->grid_waves : b->degrid_waves;
   if (grid) {
     if (nw == 4) return run_batch_grid<NP, TapT, 4>(b, flags, s);
+    if (nw == 6) return run_batch_grid<NP, TapT, 6>(b, flags, s);
     if (nw == 8) return run_batch_grid<NP, TapT, 8>(b, flags, s);
     return run_batch_grid<NP, TapT, 16>(b, flags, s);
   }
   if (nw == 4) return run_batch_degrid<NP, TapT, 4>(b, flags, s);
+  if (nw == 6) return run_batch_degrid<NP, TapT, 6>(b, flags, s);
   if (nw == 8) return run_batch_degrid<NP, TapT, 8>(b, flags, s);
   return run_batch_degrid<NP, TapT, 16>(b, flags, s);
 }

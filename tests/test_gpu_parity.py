@@ -200,7 +200,7 @@ def test_c2_grid_parity(c2_case, max_chunk, variant):
         assert rel(got[q], want[q]) < TOL, q
 
 
-@pytest.mark.parametrize("waves,group", [(4, 1), (8, 1), (16, 1), (8, 3), (16, 64), (4, 4096)])
+@pytest.mark.parametrize("waves,group", [(4, 1), (6, 1), (8, 1), (16, 1), (8, 3), (6, 5), (16, 64), (4, 4096)])
 def test_c2_launch_shapes(c2_case, waves, group):
     """Every waves-per-workgroup setting of the banded grid and the degrid, and XCD item groupings
     with a padded tail (items not a multiple of 8 x group), give the oracle result."""
