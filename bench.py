@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--grid-variant", choices=["auto", "atomic", "banded"], default="auto")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-field section")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-kernel section")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 20M-row major-cycle section")
     ap.add_argument("--surrogate-kernels", type=int, default=200_000,
                     help="teacher kernels the network is trained on")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -203,6 +204,10 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(max(2, args.steps // 2), 1)
         log(f"batched step timed: {out['batched']['ms_per_step']:.1f} ms")
+    if not args.no_scale:
+        torch.cuda.empty_cache()
+        out["scale"] = bench_scale(2, 1)
+        log(f"major-cycle step timed: {out['scale']['ms_per_step']:.1f} ms")
     if not args.no_surrogate:
         torch.cuda.empty_cache()
         out["surrogate"] = bench_surrogate(args.surrogate_kernels)
@@ -305,6 +310,81 @@ def bench_batched(steps, warmup):
             "hip_graph": True, "work_items": bg.work_items + bd.work_items,
             "grid_ms": ev[0].elapsed_time(ev[1]), "degrid_ms": ev[2].elapsed_time(ev[3]),
             "setup_s": t_setup, "image_rel_err_f16_vs_f32": err}
+
+
+def bench_scale(steps, warmup):
+    """The same step at the major-cycle scale: 8192^2 x 4 grid, 128 w-planes (supports 16-48),
+    20M rows (36 antennas x 288 channels x 8 h), a 1000-component model predicted through the
+    degridding kernels; plan -> grid -> FFT -> taper -> taper -> inverse FFT -> degrid."""
+    import torch
+
+    import synth
+    from paper_2206_15117_amd import autotune
+    from paper_2206_15117_amd import polgrid as pg
+
+    w = synth.config5()
+    launch = autotune.apply(w.geom, 4, pg.STORE_F32)
+    g = launch.geom
+    jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=w.eps_null)
+    kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones)
+    torch.cuda.synchronize()
+    t_kernels = time.perf_counter() - t0
+    uvw = torch.from_numpy(w.uvw).cuda()
+    n = g.n
+    model = torch.zeros((4, n, n), dtype=torch.float32, device="cuda")
+    jj = np.clip(np.round(w.src_l / g.cell).astype(int) + n // 2, 0, n - 1)
+    ii = np.clip(np.round(w.src_m / g.cell).astype(int) + n // 2, 0, n - 1)
+    idx = torch.from_numpy((ii * n + jj).astype(np.int64)).cuda()
+    for q in range(4):
+        model[q].view(-1).index_add_(0, idx, torch.from_numpy(w.src_iquv[:, q].astype(np.float32)).cuda())
+    vis = pg.predict(autotune.plan(kd, uvw, launch), kd, model)
+    del model
+    grid_buf = torch.empty((4, n, n), dtype=torch.complex64, device="cuda")
+    fft_buf = torch.empty_like(grid_buf)
+    img = torch.empty((4, n, n), dtype=torch.float32, device="cuda")
+    vis_out = torch.empty_like(vis)
+    ev = {k: [] for k in ("plan", "grid", "fft", "degrid")}
+
+    def step(record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record()
+        p = autotune.plan(kg, uvw, launch)
+        e[1].record()
+        pg.grid(p, kg, vis, out=grid_buf, fftshift=True)
+        e[2].record()
+        pg.taper(kg, torch.fft.fft2(grid_buf), img, pg.TAPER_IMAGE, float(p.n_kept))
+        pg.taper(kd, img, fft_buf, pg.TAPER_PREDICT)
+        gm = torch.fft.ifft2(fft_buf, norm="forward")
+        e[3].record()
+        pg.degrid(p, kd, gm, out=vis_out, fftshift=True)
+        e[4].record()
+        if record:
+            for k, (a, b) in zip(ev, [(0, 1), (1, 2), (2, 3), (3, 4)]):
+                ev[k].append((e[a], e[b]))
+        return p
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p = step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    _, _, items = p.arrays()
+    items = items.cpu().numpy()
+    s2 = int((g.support.astype(np.int64)[items[:, 0]] ** 2 * (items[:, 4] - items[:, 3])).sum())
+    return {"workload": f"major cycle: {n}x{n}x4, {g.nplanes} w-planes (supports {int(g.support.min())}-"
+                        f"{int(g.support.max())}, os 8), 36 antennas x {w.extra['n_chan']} channels x 8 h, "
+                        f"{w.nvis} rows, {len(w.src_l)}-component model, one kernel set for the band",
+            "rows": w.nvis, "n_kept": p.n_kept, "n_items": p.n_items, "value": w.nvis / wall, "unit": "vis/s",
+            "ms_per_step": 1e3 * wall, "breakdown_ms": ms, "make_kernels_s": t_kernels,
+            "grid_tflops": 128.0 * s2 / (ms["grid"] * 1e-3) / 1e12,
+            "rows_per_s_grid_plus_degrid": w.nvis / ((ms["grid"] + ms["degrid"]) * 1e-3)}
 
 
 def bench_surrogate(n_kernels):

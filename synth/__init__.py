@@ -397,3 +397,33 @@ def config4(seed: int = SEED_BASE + 4, nvis: int = 20000) -> SurrogateSetup:
     iquv[:, 0] = c1.src_iquv[:, 0]
     return SurrogateSetup(geom=geom, leakage=leak, w_max=200.0, nu_lo=700e6, nu_hi=1800e6, nu_eval=700e6,
                           pa_eval=0.4, uvw=c1.uvw, src_l=c1.src_l, src_m=c1.src_m, src_iquv=iquv)
+
+
+# --------------------------------------------------------------------------- c5: major cycle at scale
+
+def config5(seed: int = SEED_BASE + 5, nvis: int = 20_000_000, n: int = 8192, cell: float = 1.76 * ARCSEC,
+            nplanes: int = 128, nchan: int = 288, f0: float = 1.2955e9, df: float = 1e6, ndump: int = 110,
+            nsrc: int = 1000, mk: int = 256) -> Workload:
+    """Major cycle at scale: 8192^2 x 4, 128 w-planes, the 36-antenna array over 8 h with `ndump`
+    dumps in each of `nchan` 1 MHz channels from f0 (one kernel set for all channels, the beams
+    averaged over the band), padded with further dumps to `nvis` rows; a 1000-component polarised
+    point model within 1 degree.  Rows are channel-major, then time-major."""
+    rng = np.random.default_rng(seed)
+    enu = antennas_in_disk(36, 1500.0, rng)
+    nbl = 36 * 35 // 2
+    per_chan = max(ndump, -(-nvis // (nbl * nchan)))
+    ha = np.linspace(-4.0, 4.0, per_chan) * (15.0 * DEG)
+    uvw = np.empty((nchan * per_chan * nbl, 3))
+    for c in range(nchan):
+        uvw[c * per_chan * nbl:(c + 1) * per_chan * nbl] = uvw_tracks(enu, ASKAP_LAT, -45.0 * DEG, ha, f0 + c * df)
+    uvw = np.ascontiguousarray(uvw[:nvis])
+    fov = n * cell
+    w_max = math.ceil(np.abs(uvw[:, 2]).max() / 100.0) * 100.0
+    planes = linear_w_planes(nplanes, w_max)
+    support = support_rule(planes, fov)
+    geom = Geometry(n=n, cell=cell, os=8, w_planes=planes, support=support,
+                    tile=default_tiles(support, 4), aa_support=7, mk=mk)
+    beam = seeded_leakage_beam(1.0 * DEG, rng)
+    sl, sm, iquv = polarised_sources(nsrc, 1.0 * DEG, rng)
+    return Workload(f"c5-majorcycle-{n}", geom, uvw, 4, sl, sm, iquv, beam, 0.2,
+                    extra={"freq_hz": f0 + 0.5 * (nchan - 1) * df, "n_chan": nchan, "dumps_per_chan": per_chan})
