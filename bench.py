@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 ALU_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak (packed FMA)
 HBM_PEAK_GBS = 8000.0
+# L2 -> CU bandwidth derived from the chip's organisation: 8 XCDs x 16 L2 channels x 128 B/clk x 2.4 GHz
+L2_PEAK_TBS = 8 * 16 * 128 * 2.4e9 / 1e12
 
 
 def parse():
@@ -174,6 +176,7 @@ def main():
     s2_items = g.support.astype(np.int64)[items[:, 0]] ** 2
     s2_sum = int((s2_items * (items[:, 4] - items[:, 3])).sum())
     flops = float(8 * 16 * s2_sum)
+    tap_bytes = float(16 * 8 * s2_sum)
     bytes_alg = p.n_kept * (24 + 32) + 4 * n * n * 8 + int(kg.plane_offset[-1]) * 8
     dom = "grid" if ms["grid"] >= ms["degrid"] else "degrid"
     achieved = flops / (ms[dom] * 1e-3) / 1e12
@@ -196,7 +199,10 @@ def main():
         "rows_per_s_grid_plus_degrid": w.nvis / ((ms["grid"] + ms["degrid"]) * 1e-3),
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic,
-                     "hbm_frac_alg": bytes_alg / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "hbm_frac_alg": bytes_alg / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     # every kept row streams its S^2 x 16 table entries (8 B each) from L2/L1
+                     "tap_stream_TBps": {k: tap_bytes / (ms[k] * 1e-3) / 1e12 for k in ("grid", "degrid")},
+                     "l2_peak_TBps_derived": L2_PEAK_TBS},
         "source_hash": src,
     }
     if not args.no_batched:
