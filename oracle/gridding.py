@@ -17,7 +17,7 @@ from .geometry import locate
 def grid(geom, tables, uvw, vis) -> np.ndarray:
     vis = np.asarray(vis).astype(np.complex128)
     loc = locate(geom, uvw)
-    q = tables[0].shape[0]
+    q = next(t for t in tables if t is not None).shape[0]
     g = np.zeros((q, geom.n, geom.n), dtype=np.complex128)
     for k in np.nonzero(loc["keep"])[0]:
         p, s = loc["plane"][k], loc["support"][k]
@@ -29,7 +29,7 @@ def grid(geom, tables, uvw, vis) -> np.ndarray:
 
 def degrid(geom, tables, uvw, g) -> np.ndarray:
     loc = locate(geom, uvw)
-    c = tables[0].shape[1]
+    c = next(t for t in tables if t is not None).shape[1]
     out = np.zeros((uvw.shape[0], c), dtype=np.complex128)
     for k in np.nonzero(loc["keep"])[0]:
         p, s = loc["plane"][k], loc["support"][k]

@@ -143,3 +143,73 @@ def test_batch_rejects_mixed_npol(fields):
     g4 = torch.empty((4, 128, 128), dtype=torch.complex64, device="cuda")
     with pytest.raises(pg.PolgridError, match="npol"):
         pg.batch([(f["pg_"], f["kg"], torch.from_numpy(f["vis"]).cuda(), g4), (p1, k1, v, g)])
+
+
+# ------------------------------------------------------------------ full size: 16 fields, 16.1M rows
+
+def test_full_size_batched_fields_sampled():
+    """The 16-field workload (4096^2 x 4 each, float16 tables, 16.1M rows) in the benchmark's launch
+    configuration: one persistent grid launch over all fields with visibilities that are zero except
+    a seeded sample in the smallest and the largest field; those two grids against the oracle (its
+    tables rounded to float16), every other grid exactly zero; then one persistent degrid launch,
+    sampled rows of the same two fields against the oracle."""
+    from oracle import geometry
+    from paper_2206_15117_amd import autotune
+
+    pg.use_torch_allocator(True)
+    ws = synth.config3()
+    nf = len(ws)
+    n = ws[0].geom.n
+    counts = [w.nvis for w in ws]
+    check = sorted({int(np.argmin(counts)), int(np.argmax(counts))})
+    rng = np.random.default_rng(31)
+    fields, samples, tabs = [], {}, {}
+    for f, w in enumerate(ws):
+        launch = autotune.apply(w.geom, 4, pg.STORE_F16)
+        g = launch.geom
+        w.geom = g
+        jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
+        kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=0.2, storage=pg.STORE_F16)
+        kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones, storage=pg.STORE_F16)
+        uvw = torch.from_numpy(w.uvw).cuda()
+        pgr, pdg = autotune.batch_plans(kg, kd, uvw, launch)
+        vis = np.zeros((w.nvis, 4), np.complex64)
+        if f in check:
+            loc = geometry.locate(g, w.uvw)
+            cnt = np.bincount(loc["plane"][loc["keep"]], minlength=g.nplanes)
+            planes = sorted({int(np.argmax(cnt)), int(np.flatnonzero(cnt)[0])})
+            s = np.sort(np.concatenate([rng.choice(np.flatnonzero((loc["plane"] == q) & loc["keep"]),
+                                                   min(60, int(cnt[q])), replace=False) for q in planes]))
+            vis[s] = synth.random_vis(len(s), 4, rng)
+            samples[f] = s
+            tabs[f] = (kernels.round_tables(kernels.make_tables(g, mueller.phi_grid(jones, 0.2), planes=planes),
+                                            np.float16),
+                       kernels.round_tables(kernels.make_tables(g, mueller.phi_degrid(jones), planes=planes),
+                                            np.float16))
+        fields.append(dict(w=w, kg=kg, kd=kd, pg_=pgr, pd=pdg, vis=torch.from_numpy(vis).cuda()))
+    grids = torch.empty((nf, 4, n, n), dtype=torch.complex64, device="cuda")
+    b = pg.batch([(f["pg_"], f["kg"], f["vis"], grids[i]) for i, f in enumerate(fields)])
+    b.grid(fftshift=True)
+    sign = ((-1.0) ** (np.arange(n)[:, None] + np.arange(n)[None, :]))[None]
+    for i in range(nf):
+        if i in check:
+            w = fields[i]["w"]
+            s = samples[i]
+            want = gridding.grid(w.geom, tabs[i][0], w.uvw[s], fields[i]["vis"].cpu().numpy()[s]) * sign
+            got = grids[i].cpu().numpy()
+            for q in range(4):
+                assert rel(got[q], want[q]) < TOL, (i, q)
+        else:
+            assert float(grids[i].abs().max()) == 0.0, i
+    gen = torch.Generator(device="cuda").manual_seed(32)
+    gin = torch.randn((nf, 4, n, n), dtype=torch.complex64, device="cuda", generator=gen)
+    outs = [torch.empty((f["w"].nvis, 4), dtype=torch.complex64, device="cuda") for f in fields]
+    bd = pg.batch([(f["pd"], f["kd"], outs[i], gin[i]) for i, f in enumerate(fields)])
+    bd.degrid(fftshift=True)
+    for i in check:
+        w = fields[i]["w"]
+        s = samples[i]
+        want = gridding.degrid(w.geom, tabs[i][1], w.uvw[s], gin[i].cpu().numpy().astype(np.complex128) * sign)
+        got = outs[i].cpu().numpy()[s]
+        for c in range(4):
+            assert rel(got[:, c], want[:, c]) < TOL, (i, c)

@@ -1,11 +1,12 @@
-"""Parity at the full full-pol workload (2048^2 x 4, 32 planes, supports 16-48, os 8, 2.3M rows),
-in the launch configuration the benchmark times (the autotuned tiles, chunk length and waves per
-workgroup, centring folded into grid/degrid).
+"""Parity at full size, in the launch configuration the benchmark times (the autotuned tiles, chunk
+length, waves per workgroup and XCD grouping, centring folded into grid/degrid):
+  c2  full-pol 2048^2 x 4, 32 planes, supports 16-48, os 8, 2.3M rows;
+  c5  major cycle 8192^2 x 4, 128 planes, supports 16-48, os 8, 20M rows (288 channels).
 
-The oracle cannot grid 2.3M rows in seconds, so: the plan is compared bit-exactly in full; grid
-and degrid are compared on a seeded sample of rows drawn from three planes (the densest plane, a
-mid plane and an S = 48 plane), with every other visibility set to zero for grid; the adjoint
-identity is checked over all rows.
+The oracle cannot grid millions of rows in seconds, so: the plan is compared bit-exactly in full;
+grid and degrid are compared on a seeded sample of rows drawn from three planes (the densest
+plane, a mid plane and an S = 48 plane), with every other visibility set to zero for grid; the
+adjoint identity is checked over all rows.
 """
 import numpy as np
 import pytest
@@ -26,11 +27,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.fixture(scope="module")
-def full():
+@pytest.fixture(scope="module", params=["c2", "c5"])
+def full(request):
     from paper_2206_15117_amd import autotune
 
-    w = synth.config2()
+    w = synth.config2() if request.param == "c2" else synth.config5()
     launch = autotune.apply(w.geom, 4, pg.STORE_F32)
     g = launch.geom
     w.geom = g
