@@ -88,19 +88,6 @@ def test_import_applies_cell_scale(small):
     assert torch.count_nonzero(e.export_planes(0, 1)).item() == 0
 
 
-def test_features_layout():
-    x = sg.features(np.array([-200.0, 100.0]), 1250e6, np.array([0.0, math.pi / 2]), np.array([0, 15]),
-                    200.0, 700e6, 1800e6)
-    assert x.shape == (2, sg.n_features()) == (2, 24) and x.dtype == np.float32
-    np.testing.assert_allclose(x[:, 0], [-1.0, 0.5])
-    np.testing.assert_allclose(x[:, 1], [0.0, 0.0], atol=1e-7)
-    np.testing.assert_allclose(x[:, 2:4], [[0.0, 1.0], [1.0, 0.0]], atol=1e-7)
-    np.testing.assert_allclose(x[:, 4:6], [[0.0, 1.0], [0.0, -1.0]], atol=1e-7)
-    np.testing.assert_allclose(x[:, 6], [0.56, 0.56], rtol=1e-6)
-    np.testing.assert_allclose(x[:, 7], [1.0, 0.25])
-    assert x[0, 8] == 1.0 and x[1, 23] == 1.0 and x[:, 8:].sum() == 2.0
-
-
 def test_teacher_pairs_are_make_kernels_cells():
     """A teacher call returns the FFT generator's cells for its (w, nu, pa) draw, row = plane * 16 + cell."""
     s = synth.config4()
