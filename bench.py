@@ -14,7 +14,6 @@ Prints one JSON line.
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time

@@ -4,7 +4,6 @@ training pairs, and what the trained network gains over nearest-plane kernels.
 Expected values come from the FP64 oracle (kernel tables, direct Fourier transforms); the
 network is trained here, on the GPU, by the library's own forward/backward/Adam kernels.
 """
-import math
 import time
 
 import numpy as np
