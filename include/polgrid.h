@@ -67,7 +67,8 @@ extern "C" {
 #define PG_STOKES_PAPER 1 /* U = i (XY + YX)/2 as printed in Eq. 4 */
 
 /* pg_grid / pg_degrid flags */
-#define PG_ACCUMULATE 1 /* pg_grid: add onto the existing grid instead of overwriting it */
+#define PG_ACCUMULATE 1 /* pg_grid: add onto the existing grid instead of overwriting it;
+                           pg_degrid: add onto vis_out (dropped rows keep their values) */
 #define PG_FFTSHIFT 2   /* the grid in memory is G(X,Y) (-1)^(X+Y): the centring modulation
                            the FFT needs is folded into the grid flush / degrid gather */
 #define PG_VARIANT_ATOMIC 4 /* pg_grid: force the LDS-atomic accumulation kernel */
@@ -185,7 +186,8 @@ int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, 
             void* stream);
 
 /* Degridding, the exact adjoint of pg_grid (Sec. 3.2, degridding stage):
- *   V_{k,c} = sum_q sum_{X,Y} conj(T_{p_k,q,c}(...)) G_q(X, Y); dropped visibilities get 0.
+ *   V_{k,c} = sum_q sum_{X,Y} conj(T_{p_k,q,c}(...)) G_q(X, Y); dropped visibilities get 0
+ *   (with PG_ACCUMULATE: V_{k,c} is added to vis_out and dropped rows are left alone).
  * grid: complex64 [npol][n][n]; vis_out: complex64 [nvis][npol].  Enqueue only. */
 int pg_degrid(const pg_plan* p, const pg_kernels* k, const void* grid, void* vis_out, int32_t flags,
               void* stream);
@@ -250,6 +252,27 @@ int pg_mlp_copy(const pg_mlp* m, int32_t what, int32_t layer, void* dst, void* s
 int pg_mlp_load(pg_mlp* m, int32_t layer, const float* w, const float* b, void* stream);
 void pg_mlp_destroy(pg_mlp* m);
 
+/* ------------------------------------------------------------------ Hogbom minor cycle
+ * The minor cycle of Cotton-Schwab clean (Sec. 2.1; Hogbom's algorithm), run on the device with no
+ * host round trip.  Each iteration takes the masked pixel of largest |I| (plane 0 of residual;
+ * ties go to the lowest pixel index); if that value is below `threshold` (or no pixel is masked
+ * in) the cycle stops; otherwise it records the component v_q = gain x residual[q][peak] for
+ * every plane q, adds it to model[q][peak] (model may be NULL), and subtracts
+ * v_q x psf[y - py + n/2][x - px + n/2] from residual[q] wherever the shifted point-spread function
+ * overlaps the image within `psf_patch` pixels of the peak (psf_patch <= 0: no limit).  Products
+ * and differences are each rounded to float32 (no fused multiply-add), so a float32 reference
+ * reproduces the cycle exactly.
+ *   residual  float32 [npol][n][n], in/out;  psf float32 [n][n], peak at (n/2, n/2);
+ *   mask      uint8 [n][n] (non-zero = cleanable; the paper masks where the beam is below a
+ *             fraction eps of its peak, Sec. 3.3) or NULL for every pixel;
+ *   comp_pos  int32 [max_iter] flat pixel indices, comp_val float32 [max_iter][npol];
+ *   n_comp    int32 [1] (device): the number of components found.
+ * All pointers are device memory.  Enqueue only (3 launches per iteration of the budget; the
+ * launches after the stop return at once).  Errors: PG_EINVAL, PG_ENOMEM, PG_EHIP. */
+int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n, int32_t npol, float gain,
+              float threshold, int32_t psf_patch, int32_t max_iter, int32_t* comp_pos, float* comp_val, float* model,
+              int32_t* n_comp, void* stream);
+
 /* ------------------------------------------------------------------ batched launch
  * Many fields (channels or mosaic pointings, each with its own plan, kernels, visibilities and
  * grid; uneven visibility counts) gridded or degridded by ONE persistent launch: workgroups pull
@@ -281,8 +304,9 @@ void pg_batch_destroy(pg_batch* b);
  * PG_TAPER_IMAGE:   in complex64 [npol][n][n] = FFT of a PG_FFTSHIFT grid;
  *                   out float32 [npol][n][n] = Re((-1)^(i+j) in) / (AA(l_j) AA(m_i)) / weight_sum.
  * PG_TAPER_PREDICT: in float32 [npol][n][n] model; out complex64 [npol][n][n] =
- *                   (-1)^(i+j) model / (AA AA), ready for an unnormalised inverse FFT
- *                   whose result is a PG_FFTSHIFT grid.
+ *                   weight_sum x (-1)^(i+j) model / (AA AA), ready for an unnormalised inverse
+ *                   FFT whose result is a PG_FFTSHIFT grid (weight_sum is a scale here: 1 for a
+ *                   plain prediction, -1 to subtract the model with PG_ACCUMULATE degridding).
  * Enqueue only.  Errors: PG_EINVAL. */
 int pg_taper(const pg_kernels* k, const void* in, void* out, int32_t direction, double weight_sum,
              void* stream);

@@ -379,7 +379,7 @@ int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, 
 
 int pg_degrid(const pg_plan* p, const pg_kernels* k, const void* grid, void* vis_out, int32_t flags, void* stream) {
   g_error.clear();
-  int rc = check_run(p, k, grid, vis_out, flags, PG_FFTSHIFT);
+  int rc = check_run(p, k, grid, vis_out, flags, PG_ACCUMULATE | PG_FFTSHIFT);
   if (rc != PG_OK) return rc;
   if (!grid) return fail(PG_EINVAL, "grid must be non-NULL");
   PG_HIP(launch_degrid(p, k, static_cast<const float2*>(grid), static_cast<float2*>(vis_out), flags,
@@ -485,7 +485,34 @@ int pg_taper(const pg_kernels* k, const void* in, void* out, int32_t direction, 
   if (direction != PG_TAPER_IMAGE && direction != PG_TAPER_PREDICT) return fail(PG_EINVAL, "unknown taper direction");
   if (direction == PG_TAPER_IMAGE && (!(weight_sum > 0.0) || !is_finite(weight_sum)))
     return fail(PG_EINVAL, "weight_sum must be positive and finite");
+  if (direction == PG_TAPER_PREDICT && !is_finite(weight_sum)) return fail(PG_EINVAL, "scale must be finite");
   PG_HIP(launch_taper(k, in, out, direction, weight_sum, static_cast<hipStream_t>(stream)), "taper");
+  return PG_OK;
+}
+
+int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n, int32_t npol, float gain,
+              float threshold, int32_t psf_patch, int32_t max_iter, int32_t* comp_pos, float* comp_val, float* model,
+              int32_t* n_comp, void* stream) {
+  g_error.clear();
+  if (!residual || !psf || !comp_pos || !comp_val || !n_comp)
+    return fail(PG_EINVAL, "residual, psf, comp_pos, comp_val and n_comp must be non-NULL");
+  if (n < 2 || n > 16384 || (n & 1)) return fail(PG_EINVAL, "n must be even and in [2, 16384]");
+  if (npol < 1 || npol > 4) return fail(PG_EINVAL, "npol must be in [1, 4]");
+  if (!(gain > 0.0f && gain <= 1.0f)) return fail(PG_EINVAL, "gain must be in (0, 1]");
+  if (!(threshold >= 0.0f) || !std::isfinite(threshold)) return fail(PG_EINVAL, "threshold must be finite and >= 0");
+  if (max_iter < 0 || max_iter > (1 << 20)) return fail(PG_EINVAL, "max_iter must be in [0, 2^20]");
+  const int patch = (psf_patch <= 0 || psf_patch > n) ? n : psf_patch;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    DevBuf scratch;
+    if (!scratch.alloc(256 + 8 * static_cast<size_t>(std::max(max_iter, 1)), s))
+      return fail(PG_ENOMEM, "device allocation failed in hogbom");
+    PG_HIP(launch_hogbom(residual, psf, mask, n, npol, gain, threshold, patch, max_iter, comp_pos, comp_val, model,
+                         n_comp, scratch.p, s),
+           "hogbom");
+  } catch (...) {
+    return fail(PG_ENOMEM, "exception in hogbom");
+  }
   return PG_OK;
 }
 

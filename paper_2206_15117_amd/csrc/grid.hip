@@ -487,7 +487,12 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
       if (lane == 0) {
 #pragma unroll
         for (int c = 0; c < NP; ++c)
-          vis_out[static_cast<size_t>(k) * NP + c] = make_float2(acc[2 * c], acc[2 * c + 1]);
+          if (flags & PG_ACCUMULATE) {
+            float2& o = vis_out[static_cast<size_t>(k) * NP + c];
+            o = make_float2(o.x + acc[2 * c], o.y + acc[2 * c + 1]);
+          } else {
+            vis_out[static_cast<size_t>(k) * NP + c] = make_float2(acc[2 * c], acc[2 * c + 1]);
+          }
       }
     }
   }
@@ -553,12 +558,12 @@ __global__ void taper_image_kernel(const float2* __restrict__ in, float* __restr
 }
 
 __global__ void taper_predict_kernel(const float* __restrict__ in, float2* __restrict__ out, int n,
-                                     const double* __restrict__ inv_aa) {
+                                     const double* __restrict__ inv_aa, double scale) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (j >= n) return;
   const size_t idx = (static_cast<size_t>(blockIdx.z) * n + i) * n + j;
-  const double sc = inv_aa[i] * inv_aa[j] * (((i + j) & 1) ? -1.0 : 1.0);
+  const double sc = scale * inv_aa[i] * inv_aa[j] * (((i + j) & 1) ? -1.0 : 1.0);
   out[idx] = make_float2(static_cast<float>(in[idx] * sc), 0.0f);
 }
 
@@ -741,7 +746,7 @@ hipError_t launch_grid(const pg_plan* p, const pg_kernels* k, const float2* vis,
 
 hipError_t launch_degrid(const pg_plan* p, const pg_kernels* k, const float2* grid, float2* vis, int flags,
                          hipStream_t s) {
-  if (p->nvis > p->n_kept) {
+  if (p->nvis > p->n_kept && !(flags & PG_ACCUMULATE)) {  // accumulating leaves dropped rows as they are
     const int64_t nd = p->nvis - p->n_kept;
     hipLaunchKernelGGL(zero_dropped, dim3(static_cast<unsigned>((nd + 255) / 256)), dim3(256), 0, s,
                        p->perm.as<int32_t>(), p->n_kept, p->nvis, k->npol, vis);
@@ -762,7 +767,7 @@ hipError_t launch_taper(const pg_kernels* k, const void* in, void* out, int dire
                        static_cast<float*>(out), k->n, k->inv_aa.as<double>(), 1.0 / weight_sum);
   } else {
     hipLaunchKernelGGL(taper_predict_kernel, grid, dim3(256), 0, s, static_cast<const float*>(in),
-                       static_cast<float2*>(out), k->n, k->inv_aa.as<double>());
+                       static_cast<float2*>(out), k->n, k->inv_aa.as<double>(), weight_sum);
   }
   return hipGetLastError();
 }

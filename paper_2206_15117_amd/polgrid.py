@@ -75,6 +75,8 @@ EXPORTS = {
     "pg_batch_destroy": (None, [c_void_p]),
     "pg_kernels_write_cell": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "pg_kernels_alloc": (c_int, [POINTER(PgKernelSpec), c_void_p, POINTER(c_void_p)]),
+    "pg_hogbom": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, ctypes.c_float, c_int32,
+                          c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pg_kernels_export": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "pg_kernels_import": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "pg_mlp_create": (c_int, [c_int32, c_int32, c_int32, c_int64, c_int32, ctypes.c_uint64, c_void_p,
@@ -327,16 +329,19 @@ def grid(p: Plan, k: Kernels, vis, out=None, accumulate: bool = False, fftshift:
     return out
 
 
-def degrid(p: Plan, k: Kernels, g, out=None, fftshift: bool = False, stream=None):
+def degrid(p: Plan, k: Kernels, g, out=None, fftshift: bool = False, accumulate: bool = False, stream=None):
     import torch
 
     if g.dtype != torch.complex64 or tuple(g.shape) != _grid_shape(k) or not g.is_contiguous():
         raise ValueError("grid must be contiguous complex64 [npol, n, n]")
     if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs out")
         out = torch.empty((p.nvis, k.npol), dtype=torch.complex64, device=g.device)
     elif out.dtype != torch.complex64 or tuple(out.shape) != (p.nvis, k.npol) or not out.is_contiguous():
         raise ValueError("out must be contiguous complex64 [nvis, npol]")
-    _check(lib().pg_degrid(p.handle, k.handle, _ptr(g), _ptr(out), FFTSHIFT if fftshift else 0, _stream(stream)))
+    flags = (FFTSHIFT if fftshift else 0) | (ACCUMULATE if accumulate else 0)
+    _check(lib().pg_degrid(p.handle, k.handle, _ptr(g), _ptr(out), flags, _stream(stream)))
     return out
 
 
@@ -356,15 +361,42 @@ def image(p: Plan, k: Kernels, vis, weight_sum: float, grid_buf=None, out=None):
     return taper(k, f, out, TAPER_IMAGE, weight_sum)
 
 
-def predict(p: Plan, k: Kernels, model, out=None, buf=None):
-    """Model visibilities: taper correction -> unnormalised inverse FFT -> degrid."""
+def predict(p: Plan, k: Kernels, model, out=None, buf=None, subtract: bool = False):
+    """Model visibilities: taper correction -> unnormalised inverse FFT -> degrid.  With subtract,
+    out -= the model visibilities (dropped rows untouched)."""
     import torch
 
     if buf is None:
         buf = torch.empty(_grid_shape(k), dtype=torch.complex64, device=model.device)
-    taper(k, model, buf, TAPER_PREDICT)
+    taper(k, model, buf, TAPER_PREDICT, -1.0 if subtract else 1.0)
     g = torch.fft.ifft2(buf, norm="forward")
-    return degrid(p, k, g, out=out, fftshift=True)
+    return degrid(p, k, g, out=out, fftshift=True, accumulate=subtract)
+
+
+def hogbom(residual, psf, mask=None, gain: float = 0.1, threshold: float = 0.0, max_iter: int = 1000,
+           psf_patch: int = 0, model=None, stream=None):
+    """Hogbom minor cycle on the device (pg_hogbom): residual float32 [npol, n, n] is cleaned in
+    place; returns (component pixel indices int32 [m], component values float32 [m, npol])."""
+    import torch
+
+    npol, n = residual.shape[0], residual.shape[-1]
+    if residual.dtype != torch.float32 or not residual.is_contiguous() or residual.shape[1] != n:
+        raise ValueError("residual must be contiguous float32 [npol, n, n]")
+    if psf.dtype != torch.float32 or tuple(psf.shape) != (n, n) or not psf.is_contiguous():
+        raise ValueError("psf must be contiguous float32 [n, n]")
+    if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != (n, n) or not mask.is_contiguous()):
+        raise ValueError("mask must be contiguous uint8 [n, n]")
+    if model is not None and (model.dtype != torch.float32 or tuple(model.shape) != tuple(residual.shape)
+                              or not model.is_contiguous()):
+        raise ValueError("model must be contiguous float32 like residual")
+    pos = torch.empty(max(max_iter, 1), dtype=torch.int32, device=residual.device)
+    val = torch.empty((max(max_iter, 1), npol), dtype=torch.float32, device=residual.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=residual.device)
+    _check(lib().pg_hogbom(_ptr(residual), _ptr(psf), _ptr(mask), int(n), int(npol), ctypes.c_float(gain),
+                           ctypes.c_float(threshold), int(psf_patch), int(max_iter), _ptr(pos), _ptr(val),
+                           _ptr(model), _ptr(cnt), _stream(stream)))
+    m = int(cnt.item())
+    return pos[:m], val[:m]
 
 
 class Batch:
