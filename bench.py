@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-field section")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-kernel section")
     ap.add_argument("--no-scale", action="store_true", help="skip the 20M-row major-cycle section")
+    ap.add_argument("--no-clean", action="store_true", help="skip the Cotton-Schwab clean section")
     ap.add_argument("--surrogate-kernels", type=int, default=200_000,
                     help="teacher kernels the network is trained on")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -204,6 +205,9 @@ def main():
                      "l2_peak_TBps_derived": L2_PEAK_TBS},
         "source_hash": src,
     }
+    if not args.no_clean:
+        out["clean"] = bench_clean(w, g, p, kg, kd, vis)
+        log(f"clean timed: {out['clean']['ms_total']:.1f} ms")
     if not args.no_batched:
         del grid_buf, fft_buf, img, vis_out
         torch.cuda.empty_cache()
@@ -298,6 +302,10 @@ def bench_batched(steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     rows = sum(w.nvis for w in fields)
+    s2 = 0
+    for (pgr, _), w in zip(ps, fields):
+        items = pgr.arrays()[2].cpu().numpy()
+        s2 += int((w.geom.support.astype(np.int64)[items[:, 0]] ** 2 * (items[:, 4] - items[:, 3])).sum())
     # image error of float16 tables against float32 tables on the smallest field
     f = int(np.argmin([w.nvis for w in fields]))
     w = fields[f]
@@ -314,7 +322,36 @@ def bench_batched(steps, warmup):
             "rows": rows, "value": rows / (ms * 1e-3), "unit": "vis/s", "ms_per_step": ms,
             "hip_graph": True, "work_items": bg.work_items + bd.work_items,
             "grid_ms": ev[0].elapsed_time(ev[1]), "degrid_ms": ev[2].elapsed_time(ev[3]),
+            "grid_tflops": 128.0 * s2 / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e12,
+            "mean_support_sq": s2 / rows,
             "setup_s": t_setup, "image_rel_err_f16_vs_f32": err}
+
+
+def bench_clean(w, g, p, kg, kd, vis, cycles=3, minor_iter=1000, eps=0.2):
+    """Cotton-Schwab clean of the 2.3M full-pol rows (50-source model): `cycles` major cycles of
+    grid -> FFT -> taper, Hogbom minor cycles of up to `minor_iter` components on the device inside
+    the beam mask (power beam >= eps of its peak, Sec. 3.3) and the taper mask, model predicted
+    and subtracted."""
+    import torch
+
+    import synth
+    from paper_2206_15117_amd import clean as cs
+
+    jones = synth.jones_on_lattice(w.beam, g.n, g.fov)            # [2][2][n][n] on the image pixels
+    power = 0.5 * (np.abs(jones) ** 2).sum(axis=(0, 1))           # Stokes-I power beam
+    mask = torch.from_numpy((power >= eps * power.max()).astype(np.uint8)).cuda()
+    psf = cs.psf(p, kg, float(p.n_kept))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = cs.cotton_schwab(p, kg, kd, vis, mask=mask, gain=0.1, cycles=cycles, minor_iter=minor_iter,
+                           cycle_factor=0.1, psf_patch=256, beam=psf)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"Cotton-Schwab clean of the {w.nvis}-row full-pol workload: {cycles} major cycles, "
+                        f"Hogbom minor cycles of up to {minor_iter} components (gain 0.1, cycle factor 0.1, "
+                        f"psf patch 256) inside the eps = {eps} beam mask",
+            "ms_total": 1e3 * dt, "ms_per_major_cycle": 1e3 * dt / cycles, "components": res.components,
+            "residual_peaks": res.peaks}
 
 
 def bench_scale(steps, warmup):

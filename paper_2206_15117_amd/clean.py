@@ -23,7 +23,9 @@ class CleanResult:
 
 def psf(plan, kernels, weight_sum: float):
     """The point-spread function: Stokes-I image of unit Stokes-I visibilities (XX = YY = 1) on the
-    same plan and kernels, float32 [n][n] with its peak normalised to one."""
+    same plan and kernels, float32 [n][n], divided by its value at the phase centre (n/2, n/2) so
+    the peak is one (the largest |value| can sit at the image edge, where the taper correction
+    amplifies rounding noise)."""
     import torch
 
     npol = kernels.npol
@@ -32,7 +34,8 @@ def psf(plan, kernels, weight_sum: float):
     if npol == 4:
         unit[:, 3] = 1.0
     img = pg.image(plan, kernels, unit, weight_sum)[0].contiguous()
-    return img / img.abs().max()
+    n = img.shape[-1]
+    return img / img[n // 2, n // 2]
 
 
 def taper_mask(kernels, aa_min: float = 0.1):
