@@ -228,8 +228,8 @@ def main():
 
 def bench_batched(steps, warmup):
     """16 channels with uneven row counts, each on its own 4096^2 x 4 grid with float16 tables:
-    grid (one persistent launch over all fields) -> FFT -> taper -> taper -> inverse FFT ->
-    degrid (one persistent launch), the whole step captured in one HIP graph and replayed."""
+    grid (one launch over all fields' work items) -> FFT -> taper -> taper -> inverse FFT ->
+    degrid (one launch), the whole step captured in one HIP graph and replayed."""
     import torch
 
     import synth
@@ -273,7 +273,7 @@ def bench_batched(steps, warmup):
         torch.fft.ifft2(model, norm="forward", out=gmodel)
         bd.degrid(fftshift=True)
 
-    # eager breakdown of the two persistent launches
+    # eager breakdown of the two batched launches
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     step()
     ev[0].record()

@@ -275,9 +275,9 @@ int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n,
 
 /* ------------------------------------------------------------------ batched launch
  * Many fields (channels or mosaic pointings, each with its own plan, kernels, visibilities and
- * grid; uneven visibility counts) gridded or degridded by ONE persistent launch: workgroups pull
- * (field, work item) pairs from a device queue ordered largest item first, so uneven fields
- * balance across the GPU (multi-field mosaics and channel-dependent beams, Sec. 2.2, Sec. 3.2).
+ * grid; uneven visibility counts) gridded or degridded by ONE launch: workgroup b takes the
+ * (field, work item) pair b of a list ordered largest item first, so uneven fields balance across
+ * the GPU (multi-field mosaics and channel-dependent beams, Sec. 2.2, Sec. 3.2).
  * All fields share npol and table storage; geometries may differ.  The launch shape (waves per
  * workgroup) is taken from the first field's plan (pg_plan_set_launch). */
 typedef struct pg_field {
@@ -288,14 +288,14 @@ typedef struct pg_field {
 } pg_field;
 typedef struct pg_batch pg_batch;
 
-/* Builds the device field table and the ordered work queue; the plans, kernels and buffers must
+/* Builds the device field table and the ordered work list; the plans, kernels and buffers must
  * outlive the batch.  Synchronises `stream`.  Errors: PG_EINVAL (NULLs, npol or storage mismatch,
  * plan/kernel geometry mismatch), PG_ENOMEM, PG_EHIP. */
 int pg_batch_create(const pg_field* fields, int32_t nfields, void* stream, pg_batch** out);
-/* Enqueue: zero every grid (unless PG_ACCUMULATE), reset the queue, one persistent grid launch.
+/* Enqueue: zero every grid (unless PG_ACCUMULATE), one grid launch over all work items.
  * Allocates nothing and calls only kernel launches, so it may be captured in a HIP graph. */
 int pg_batch_grid(const pg_batch* b, int32_t flags, void* stream);
-/* Enqueue: zero dropped visibilities, reset the queue, one persistent degrid launch.  Capturable. */
+/* Enqueue: zero dropped visibilities, one degrid launch over all work items.  Capturable. */
 int pg_batch_degrid(const pg_batch* b, int32_t flags, void* stream);
 int64_t pg_batch_work_items(const pg_batch* b);
 void pg_batch_destroy(pg_batch* b);

@@ -96,7 +96,7 @@ def apply(geom, npol, storage) -> Launch:
 
 
 def batch_plans(kernels_grid, kernels_degrid, uvw, launch: Launch):
-    """(grid plan, degrid plan) for one field of a batched launch, with the persistent kernels'
+    """(grid plan, degrid plan) for one field of a batched launch, with the batched kernels'
     waves per workgroup (a batch takes its launch shape from its first field's plan)."""
     from . import polgrid as pg
 

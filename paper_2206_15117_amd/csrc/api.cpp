@@ -201,7 +201,6 @@ int plan_impl(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_
   while (bits < 64 && (static_cast<unsigned __int128>(1) << bits) <= nbins) ++bits;  // 2^bits > max key + 1
   if ((static_cast<unsigned __int128>(1) << bits) <= nbins) return fail(PG_EUNSUPPORTED, "binning key exceeds 64 bits");
   const uint64_t drop_key = bits == 64 ? ~0ull : ((1ull << bits) - 1);
-  if (!p->counter.alloc(sizeof(int32_t) * 4, s)) return fail(PG_ENOMEM, "device allocation failed in plan");
   if (nvis == 0) {
     if (n_dropped) *n_dropped = 0;
     *out = guard.release();
@@ -442,11 +441,7 @@ int pg_batch_create(const pg_field* fields, int32_t nfields, void* stream, pg_ba
     b->n_work = static_cast<int64_t>(costs.size());
     std::vector<int2> work(costs.size());
     for (size_t i = 0; i < costs.size(); ++i) work[i] = make_int2(costs[i].field, costs[i].item);
-    int dev = 0;
-    PG_HIP(hipGetDevice(&dev), "get device");
-    PG_HIP(hipDeviceGetAttribute(&b->n_cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
-    if (!b->fields.alloc(sizeof(FieldArgs) * nfields, s) || !b->work.alloc(sizeof(int2) * std::max<size_t>(work.size(), 1), s) ||
-        !b->counter.alloc(8, s))
+    if (!b->fields.alloc(sizeof(FieldArgs) * nfields, s) || !b->work.alloc(sizeof(int2) * std::max<size_t>(work.size(), 1), s))
       return fail(PG_ENOMEM, "device allocation failed in batch_create");
     PG_HIP(hipMemcpyAsync(b->fields.p, fa.data(), sizeof(FieldArgs) * nfields, hipMemcpyHostToDevice, s), "upload fields");
     if (!work.empty())

@@ -144,7 +144,6 @@ struct pg_plan {
   pg::DevBuf perm;    // int32 [nvis]
   pg::DevBuf fine;    // int2 [n_kept]
   pg::DevBuf items;   // Item [n_items]
-  pg::DevBuf counter; // int32 work queue head for the persistent launch
 };
 
 struct pg_batch {
@@ -152,13 +151,11 @@ struct pg_batch {
   int64_t n_work = 0;
   size_t lds_bytes = 0;          // largest sub-grid over the fields
   int32_t grid_waves = 16, degrid_waves = 16;
-  int32_t n_cus = 256;
   std::vector<const pg_plan*> plans;
   std::vector<const pg_kernels*> kernels;
   std::vector<void*> vis, grids;
   pg::DevBuf fields;   // FieldArgs [nfields]
   pg::DevBuf work;     // int2 (field, item) [n_work], largest item first
-  pg::DevBuf counter;  // queue head (8 bytes, zeroed before each launch)
 };
 
 // ---- launchers implemented in the .hip files (all enqueue on `s`)

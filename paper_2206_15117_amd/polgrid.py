@@ -400,7 +400,7 @@ def hogbom(residual, psf, mask=None, gain: float = 0.1, threshold: float = 0.0, 
 
 
 class Batch:
-    """Many fields gridded or degridded by one persistent launch (pg_batch)."""
+    """Many fields gridded or degridded by one launch each way (pg_batch)."""
 
     def __init__(self, fields, stream=None):
         self._keep = list(fields)

@@ -1,4 +1,4 @@
-"""The batched persistent launch against the oracle, per field, plus HIP-graph replay."""
+"""The batched launch against the oracle, per field, plus HIP-graph replay."""
 import numpy as np
 import pytest
 
@@ -78,7 +78,7 @@ def test_batched_equals_single_field_launches(fields):
 
 
 def test_graph_replay_matches_eager(fields):
-    """grid (persistent) -> FFT -> taper captured in one HIP graph; every replay equals eager."""
+    """grid (batched) -> FFT -> taper captured in one HIP graph; every replay equals eager."""
     vis = [torch.from_numpy(f["vis"]).cuda() for f in fields]
     grids = [torch.empty((4, f["w"].geom.n, f["w"].geom.n), dtype=torch.complex64, device="cuda") for f in fields]
     imgs = [torch.empty((4, f["w"].geom.n, f["w"].geom.n), dtype=torch.float32, device="cuda") for f in fields]
@@ -149,9 +149,9 @@ def test_batch_rejects_mixed_npol(fields):
 
 def test_full_size_batched_fields_sampled():
     """The 16-field workload (4096^2 x 4 each, float16 tables, 16.1M rows) in the benchmark's launch
-    configuration: one persistent grid launch over all fields with visibilities that are zero except
+    configuration: one grid launch over all fields with visibilities that are zero except
     a seeded sample in the smallest and the largest field; those two grids against the oracle (its
-    tables rounded to float16), every other grid exactly zero; then one persistent degrid launch,
+    tables rounded to float16), every other grid exactly zero; then one degrid launch,
     sampled rows of the same two fields against the oracle."""
     from oracle import geometry
     from paper_2206_15117_amd import autotune
