@@ -275,11 +275,13 @@ int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n,
 
 /* ------------------------------------------------------------------ batched launch
  * Many fields (channels or mosaic pointings, each with its own plan, kernels, visibilities and
- * grid; uneven visibility counts) gridded or degridded by ONE launch: workgroup b takes the
- * (field, work item) pair b of a list ordered largest item first, so uneven fields balance across
- * the GPU (multi-field mosaics and channel-dependent beams, Sec. 2.2, Sec. 3.2).
+ * grid; uneven visibility counts) gridded or degridded by ONE launch over every (field, work
+ * item) pair: fields largest first, each in plan order, in groups of consecutive items (the first
+ * plan's XCD grouping) that each run on one XCD, so uneven fields balance across the GPU with
+ * one or two fields' tables in the caches at a time (multi-field mosaics and channel-dependent
+ * beams, Sec. 2.2, Sec. 3.2).
  * All fields share npol and table storage; geometries may differ.  The launch shape (waves per
- * workgroup) is taken from the first field's plan (pg_plan_set_launch). */
+ * workgroup, XCD grouping) is taken from the first field's plan (pg_plan_set_launch). */
 typedef struct pg_field {
   const pg_plan* plan;
   const pg_kernels* kernels;
@@ -297,6 +299,7 @@ int pg_batch_create(const pg_field* fields, int32_t nfields, void* stream, pg_ba
 int pg_batch_grid(const pg_batch* b, int32_t flags, void* stream);
 /* Enqueue: zero dropped visibilities, one degrid launch over all work items.  Capturable. */
 int pg_batch_degrid(const pg_batch* b, int32_t flags, void* stream);
+/* Number of (field, work item) pairs in the batch; -1 for NULL. */
 int64_t pg_batch_work_items(const pg_batch* b);
 void pg_batch_destroy(pg_batch* b);
 

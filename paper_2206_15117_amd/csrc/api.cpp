@@ -437,10 +437,43 @@ int pg_batch_create(const pg_field* fields, int32_t nfields, void* stream, pg_ba
                          f, static_cast<int32_t>(i)});
       }
     }
-    std::stable_sort(costs.begin(), costs.end(), [](const Cost& a, const Cost& c) { return a.cost > c.cost; });
+    // Fields largest first (total estimated cost), each in plan order (plane by plane, tile by
+    // tile), cut into groups of up to `group` consecutive items (the first field's XCD grouping).
+    // Group k goes to XCD k mod 8, behind that XCD's earlier groups; XCD x's j-th entry is block
+    // 8 j + x.  Shorter XCD queues are padded with no-op entries.  Field-major order keeps one or
+    // two fields' kernel tables and grids in the caches at a time; the first large field starts
+    // first and the smallest field fills the tail.
+    const int group = std::max(1, fields[0].plan->xcd_group);
+    std::vector<int64_t> field_cost(nfields, 0);
+    for (const auto& c : costs) field_cost[c.field] += c.cost;
+    std::vector<int> rank(nfields), by_cost(nfields);
+    for (int f = 0; f < nfields; ++f) by_cost[f] = f;
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) { return field_cost[x] > field_cost[y]; });
+    for (int r = 0; r < nfields; ++r) rank[by_cost[r]] = r;
+    std::stable_sort(costs.begin(), costs.end(), [&](const Cost& x, const Cost& y) { return rank[x.field] < rank[y.field]; });
+    struct Group {
+      size_t first, count;
+    };
+    std::vector<Group> groups;
+    for (size_t i = 0; i < costs.size();) {
+      size_t e = i;
+      while (e < costs.size() && e - i < static_cast<size_t>(group) && costs[e].field == costs[i].field) ++e;
+      groups.push_back({i, e - i});
+      i = e;
+    }
+    std::vector<int2> queue[8];
+    for (size_t k = 0; k < groups.size(); ++k)
+      for (size_t i = 0; i < groups[k].count; ++i) {
+        const Cost& c = costs[groups[k].first + i];
+        queue[k % 8].push_back(make_int2(c.field, c.item));
+      }
+    size_t depth = 0;
+    for (const auto& q : queue) depth = std::max(depth, q.size());
+    std::vector<int2> work(depth * 8, make_int2(-1, -1));
+    for (int x = 0; x < 8; ++x)
+      for (size_t j = 0; j < queue[x].size(); ++j) work[8 * j + x] = queue[x][j];
     b->n_work = static_cast<int64_t>(costs.size());
-    std::vector<int2> work(costs.size());
-    for (size_t i = 0; i < costs.size(); ++i) work[i] = make_int2(costs[i].field, costs[i].item);
+    b->n_blocks = static_cast<int64_t>(work.size());
     if (!b->fields.alloc(sizeof(FieldArgs) * nfields, s) || !b->work.alloc(sizeof(int2) * std::max<size_t>(work.size(), 1), s))
       return fail(PG_ENOMEM, "device allocation failed in batch_create");
     PG_HIP(hipMemcpyAsync(b->fields.p, fa.data(), sizeof(FieldArgs) * nfields, hipMemcpyHostToDevice, s), "upload fields");

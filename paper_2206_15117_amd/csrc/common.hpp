@@ -148,14 +148,15 @@ struct pg_plan {
 
 struct pg_batch {
   int32_t nfields = 0, npol = 1, storage = 0;
-  int64_t n_work = 0;
+  int64_t n_work = 0;    // (field, item) pairs
+  int64_t n_blocks = 0;  // launch size: n_work plus no-op entries that even out the XCD queues
   size_t lds_bytes = 0;          // largest sub-grid over the fields
   int32_t grid_waves = 16, degrid_waves = 16;
   std::vector<const pg_plan*> plans;
   std::vector<const pg_kernels*> kernels;
   std::vector<void*> vis, grids;
   pg::DevBuf fields;   // FieldArgs [nfields]
-  pg::DevBuf work;     // int2 (field, item) [n_work], largest item first
+  pg::DevBuf work;     // int2 (field, item) [n_blocks] in launch order; (-1, -1) = no-op
 };
 
 // ---- launchers implemented in the .hip files (all enqueue on `s`)
