@@ -44,26 +44,48 @@ struct Chunk<__half2> {
   static constexpr int E = 4;  // float16 pairs per 16-byte chunk
 };
 
+// A wave-uniform global address made opaque to the optimiser: kept in scalar registers, so a load
+// from it plus a 32-bit lane offset uses the scalar-base addressing form with no vector address
+// arithmetic (left alone, the compiler folds several such bases into one and rebuilds each address
+// with 64-bit vector adds).
+typedef const __attribute__((address_space(1))) char GlobalBytes;
+typedef float GlobalF2 __attribute__((ext_vector_type(2)));
+typedef float GlobalF4 __attribute__((ext_vector_type(4)));
+typedef unsigned GlobalU4 __attribute__((ext_vector_type(4)));
+template <typename V>
+__device__ __forceinline__ V load_global(GlobalBytes* p) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) V*>(p);
+}
+__device__ __forceinline__ GlobalBytes* uniform_base(const void* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return reinterpret_cast<GlobalBytes*>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 template <int NQC, typename TapT>
 struct TapChunks {
   static constexpr int E = NQC < Chunk<TapT>::E ? NQC : Chunk<TapT>::E;
   static constexpr int NCH = NQC / E;
-  const TapT* base;     // wave-uniform: chunk 0 of one phase block [chunk][SS][E]
-  uint32_t chunk_bytes;  // distance between chunks, SS * E * sizeof(TapT)
-  __device__ TapChunks(const TapT* ph, int ss)
-      : base(ph), chunk_bytes(static_cast<uint32_t>(ss) * E * static_cast<uint32_t>(sizeof(TapT))) {}
-  // All npol^2 taps of tap index t: one scalar base plus a 32-bit per-lane offset per chunk.
-  __device__ void load(uint32_t t, float2 (&out)[NQC]) const {
-    const uint32_t boff = t * static_cast<uint32_t>(E * sizeof(TapT));
+  static constexpr uint32_t kTapBytes = E * sizeof(TapT);  // bytes of one tap in one chunk
+  GlobalBytes* base[NCH];  // wave-uniform: chunk j of one phase block [chunk][SS][E]
+  __device__ TapChunks(const TapT* ph, int ss) {
+    const uint32_t chunk_bytes = static_cast<uint32_t>(ss) * kTapBytes;
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) base[j] = uniform_base(reinterpret_cast<const char*>(ph) + j * chunk_bytes);
+  }
+  // All npol^2 taps of tap index t: per chunk, one scalar base plus a 32-bit lane offset.
+  __device__ void load(uint32_t t, float2 (&out)[NQC]) const { load_at(t * kTapBytes, out); }
+  __device__ void load_at(uint32_t boff, float2 (&out)[NQC]) const {
 #pragma unroll
     for (int j = 0; j < NCH; ++j) {
-      const TapT* p = reinterpret_cast<const TapT*>(reinterpret_cast<const char*>(base) + boff + j * chunk_bytes);
+      GlobalBytes* p = base[j] + boff;
       if constexpr (E == 2) {
-        const float4 v = *reinterpret_cast<const float4*>(p);
+        const GlobalF4 v = load_global<GlobalF4>(p);
         out[2 * j] = make_float2(v.x, v.y);
         out[2 * j + 1] = make_float2(v.z, v.w);
       } else if constexpr (E == 4) {
-        const uint4 v = *reinterpret_cast<const uint4*>(p);
+        const GlobalU4 v = load_global<GlobalU4>(p);
         const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -72,10 +94,45 @@ struct TapChunks {
           out[4 * j + e] = __half22float2(h);
         }
       } else if constexpr (sizeof(TapT) == 8) {
-        out[j] = *reinterpret_cast<const float2*>(p);
+        const GlobalF2 v = load_global<GlobalF2>(p);
+        out[j] = make_float2(v.x, v.y);
       } else {
-        out[j] = __half22float2(*reinterpret_cast<const __half2*>(p));
+        const unsigned w = load_global<unsigned>(p);
+        __half2 h;
+        __builtin_memcpy(&h, &w, 4);
+        out[j] = __half22float2(h);
       }
+    }
+  }
+};
+
+// Lane position in a footprint walked 64 taps at a time: tap u sits at footprint row u / S, column
+// u % S, i.e. sub-grid element off = (row0 + u / S) P + col0 + u % S.  The first position is
+// computed once; every later step of 64 taps is a few adds and one compare (no division, no
+// multiply: the compiler otherwise rebuilds off, and each Stokes plane's address, with quarter-
+// rate integer multiplies).
+struct FootStep {
+  int S, dt, doff, wrap;  // dt = 64 mod S, doff = (64 / S) P + dt, wrap = P - S
+  __device__ FootStep(int S_, int P) : S(S_) {
+    const int dr = 64 / S_;
+    dt = 64 - dr * S_;
+    doff = dr * P + dt;
+    wrap = P - S_;
+  }
+};
+struct TapCursor {
+  int tx, off;
+  __device__ TapCursor(int u, int row0, int col0, float inv_s, int S, int P) {
+    const int rr = static_cast<int>((static_cast<float>(u) + 0.5f) * inv_s);
+    tx = u - rr * S;
+    off = (row0 + rr) * P + col0 + tx;
+  }
+  __device__ __forceinline__ void advance(const FootStep& st) {
+    tx += st.dt;
+    off += st.doff;
+    if (tx >= st.S) {
+      tx -= st.S;
+      off += st.wrap;
     }
   }
 };
@@ -194,13 +251,9 @@ struct BandRow {
 #pragma unroll
     for (int c = 0; c < NP; ++c) v[c] = vis[static_cast<size_t>(k) * NP + c];
   }
-  // Adds the Mueller product of tap u (0 <= u < cnt) into the LDS sub-grid: all npol reads are
-  // issued before the arithmetic and all writes after it.
-  __device__ __forceinline__ void apply(float2* lds, int u, const float2 (&tap)[NP * NP], float inv_s, int S, int P,
-                                        int WP) const {
-    const int rr = static_cast<int>((static_cast<float>(u) + 0.5f) * inv_s);
-    const int tx = u - rr * S;
-    const int off = (a + rr) * P + lx + tx;
+  // Adds the Mueller product of one tap into the LDS sub-grid at element off of each Stokes plane
+  // (planes WP apart): all npol reads are issued before the arithmetic and all writes after it.
+  __device__ __forceinline__ void apply(float2* lds, int off, const float2 (&tap)[NP * NP], int WP) const {
     float2 g[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) g[q] = lds[q * WP + off];
@@ -289,6 +342,7 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
   }
   __syncthreads();
   const int r0 = band[wave], r1 = band[wave + 1];
+  const FootStep step(S, P);
   // Metadata of 64 rows is fetched lane-parallel in one coalesced load and broadcast per row with
   // readlane, so walking the item costs one memory latency per 64 rows, not two per row.
   for (int blk = it.start; blk < it.end && r0 < r1; blk += 64) {
@@ -330,23 +384,31 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
       }
       const BandRow<NP, TapT> ra(ja, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset);
       const BandRow<NP, TapT> rb(jb, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset);
+      constexpr uint32_t TB = TapChunks<NP * NP, TapT>::kTapBytes;
       float2 ta[NP * NP], tb[NP * NP];
       const bool la = lane < ra.cnt, lb = lane < rb.cnt;
-      if (la) ra.tc.load(ra.t0 + static_cast<uint32_t>(lane), ta);
-      if (lb) rb.tc.load(rb.t0 + static_cast<uint32_t>(lane), tb);
-      if (la) ra.apply(lds, lane, ta, inv_s, S, P, WP);
+      uint32_t ba = (ra.t0 + static_cast<uint32_t>(lane)) * TB, bb = (rb.t0 + static_cast<uint32_t>(lane)) * TB;
+      if (la) ra.tc.load_at(ba, ta);
+      if (lb) rb.tc.load_at(bb, tb);
+      TapCursor ca(lane, ra.a, ra.lx, inv_s, S, P);
+      if (la) ra.apply(lds, ca.off, ta, WP);
 #pragma unroll 1
       for (int u = lane + 64; u < ra.cnt; u += 64) {
         float2 t[NP * NP];
-        ra.tc.load(ra.t0 + static_cast<uint32_t>(u), t);
-        ra.apply(lds, u, t, inv_s, S, P, WP);
+        ba += 64 * TB;
+        ra.tc.load_at(ba, t);
+        ca.advance(step);
+        ra.apply(lds, ca.off, t, WP);
       }
-      if (lb) rb.apply(lds, lane, tb, inv_s, S, P, WP);
+      TapCursor cb(lane, rb.a, rb.lx, inv_s, S, P);
+      if (lb) rb.apply(lds, cb.off, tb, WP);
 #pragma unroll 1
       for (int u = lane + 64; u < rb.cnt; u += 64) {
         float2 t[NP * NP];
-        rb.tc.load(rb.t0 + static_cast<uint32_t>(u), t);
-        rb.apply(lds, u, t, inv_s, S, P, WP);
+        bb += 64 * TB;
+        rb.tc.load_at(bb, t);
+        cb.advance(step);
+        rb.apply(lds, cb.off, t, WP);
       }
     }
   }
@@ -442,6 +504,7 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const FootStep step(S, P);
   // wave w takes rows start + w, start + w + NW, ...; metadata of 64 of them at a time comes in one
   // coalesced load and is broadcast per row with readlane
   for (int blk = it.start + wave; blk < it.end; blk += 64 * NW) {
@@ -465,13 +528,16 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
       float acc[2 * NP];
 #pragma unroll
       for (int c = 0; c < 2 * NP; ++c) acc[c] = 0.0f;
+      constexpr uint32_t TB = TapChunks<NP * NP, TapT>::kTapBytes;
+      TapCursor cur(lane, ly, lx, inv_s, S, P);
+      uint32_t boff = static_cast<uint32_t>(lane) * TB;
 #pragma unroll 2
       for (int t = lane; t < SS; t += 64) {
-        const int ty = static_cast<int>((static_cast<float>(t) + 0.5f) * inv_s);
-        const int tx = t - ty * S;
         float2 tap[NP * NP];
-        tc.load(static_cast<uint32_t>(t), tap);
-        const int off = (ly + ty) * P + lx + tx;
+        tc.load_at(boff, tap);
+        const int off = cur.off;
+        boff += 64 * TB;
+        cur.advance(step);
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
           const float2 g = lds[q * WP + off];
