@@ -173,10 +173,13 @@ void pg_plan_destroy(pg_plan* p);
  * summation order): grid_variant 0 = choose by sub-grid width, 1 = LDS-atomic accumulation,
  * 2 = row-band ownership; grid_waves and degrid_waves = waves per workgroup, 4, 6, 8 or 16;
  * xcd_group = how many consecutive work items (in plan order) run on one XCD, so that they share
- * its L2 (1 = plain order, up to 4096).  Set before the plan is shared between threads.
+ * its L2 (1 = plain order, up to 4096); grid_planes = output correlation planes per row-band
+ * workgroup, 0 (all), 1, 2 or 4: with 1 or 2, npol / grid_planes workgroups share each work item,
+ * each holding only its planes' sub-grid in LDS and reading only its rows of the 4x4 Mueller
+ * kernels (ignored where it does not divide npol).  Set before the plan is shared between threads.
  * Errors: PG_EINVAL. */
 int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves,
-                       int32_t xcd_group);
+                       int32_t xcd_group, int32_t grid_planes);
 
 /* Gridding (Sec. 3.2, Sec. 4):
  *   G_q(X,Y) (+)= sum_k sum_c T_{p_k,q,c}(X os - fine_x,k, Y os - fine_y,k) V_{k,c}.

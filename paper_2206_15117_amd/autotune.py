@@ -4,6 +4,7 @@ Searches, per geometry class (npol, storage, os, per-plane supports):
   * workgroups per CU (1-4): sets each plane's tile T to the largest sub-grid that fits
     1/k of the LDS, so every item of a launch has the same LDS footprint;
   * waves per workgroup for grid and degrid (4, 6, 8, 16);
+  * output planes per gridder workgroup (all, 2 or 1 of the four correlations);
   * the grid variant (row bands or LDS atomics) and the chunk length of work items;
   * how many consecutive work items share one XCD (and its L2), for the best shape found.
 Each candidate is timed with HIP events on a representative workload; the best choice is
@@ -19,7 +20,7 @@ from collections import namedtuple
 import numpy as np
 
 Launch = namedtuple("Launch", "geom max_chunk variant grid_waves degrid_waves xcd_group batch_grid_waves "
-                               "batch_degrid_waves")
+                               "batch_degrid_waves grid_planes")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
@@ -86,13 +87,14 @@ def apply(geom, npol, storage) -> Launch:
     cfg = tuned_config(npol, storage, geom.os, geom.support)
     g = copy.copy(geom)
     if cfg is None:
-        return Launch(g, 1024, 0, 16, 16, 1, 16, 16)
+        return Launch(g, 1024, 0, 16, 16, 1, 16, 16, 0)
     g.tile = np.asarray(cfg["grid"]["tiles"], dtype=np.int32)
     same = cfg["grid"]["wgs_per_cu"] == cfg["degrid"]["wgs_per_cu"]
     gw, dw = int(cfg["grid"]["waves"]), int(cfg["degrid"]["waves"]) if same else 16
     batch = cfg.get("batch", {})
     return Launch(g, int(cfg["grid"]["max_chunk"]), int(cfg["grid"].get("variant", 2)), gw, dw,
-                  int(cfg.get("xcd_group", 1)), int(batch.get("grid_waves", gw)), int(batch.get("degrid_waves", dw)))
+                  int(cfg.get("xcd_group", 1)), int(batch.get("grid_waves", gw)), int(batch.get("degrid_waves", dw)),
+                  int(cfg["grid"].get("planes", 0)))
 
 
 def batch_plans(kernels_grid, kernels_degrid, uvw, launch: Launch):
@@ -102,8 +104,8 @@ def batch_plans(kernels_grid, kernels_degrid, uvw, launch: Launch):
 
     pg_ = pg.plan(kernels_grid, uvw, max_chunk=launch.max_chunk)
     pd_ = pg.plan(kernels_degrid, uvw, max_chunk=launch.max_chunk)
-    pg_.set_launch(0, launch.batch_grid_waves, launch.degrid_waves, launch.xcd_group)
-    pd_.set_launch(0, launch.grid_waves, launch.batch_degrid_waves, launch.xcd_group)
+    pg_.set_launch(0, launch.batch_grid_waves, launch.degrid_waves, launch.xcd_group, launch.grid_planes)
+    pd_.set_launch(0, launch.grid_waves, launch.batch_degrid_waves, launch.xcd_group, launch.grid_planes)
     return pg_, pd_
 
 
@@ -112,7 +114,7 @@ def plan(kernels, uvw, launch: Launch):
     from . import polgrid as pg
 
     return pg.plan(kernels, uvw, max_chunk=launch.max_chunk).set_launch(0, launch.grid_waves, launch.degrid_waves,
-                                                                        launch.xcd_group)
+                                                                        launch.xcd_group, launch.grid_planes)
 
 
 def _time(fn, reps):
@@ -129,7 +131,7 @@ def _time(fn, reps):
 
 
 def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2, 3, 4),
-         waves=(4, 6, 8, 16), chunks=(256, 1024), verbose=True):
+         waves=(4, 6, 8, 16), chunks=(256, 1024), planes=(0, 2, 1), verbose=True):
     """Time every candidate; returns (best dict, list of all results)."""
     import copy
 
@@ -151,13 +153,13 @@ def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2
         for chunk in chunks:
             p = pg.plan(kg, uvw, max_chunk=chunk)
             for nw in waves:
-                for variant in (2, 1):
+                for variant, gp in [(2, q) for q in planes if q == 0 or npol % q == 0] + [(1, 0)]:
                     if variant == 1 and nw != 16:
                         continue
-                    p.set_launch(variant, nw, nw)
+                    p.set_launch(variant, nw, nw, 1, gp)
                     tg = _time(lambda: pg.grid(p, kg, vis, out=grid, fftshift=True), reps)
                     td = _time(lambda: pg.degrid(p, kd, grid, out=out, fftshift=True), reps)
-                    r = dict(wgs_per_cu=k, max_chunk=chunk, waves=nw, variant=variant,
+                    r = dict(wgs_per_cu=k, max_chunk=chunk, waves=nw, variant=variant, planes=gp,
                              grid_ms=tg, degrid_ms=td, tiles=tiles.tolist())
                     results.append(r)
                     if verbose:
@@ -165,7 +167,7 @@ def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2
     bg = min(results, key=lambda r: r["grid_ms"])
     bd = min(results, key=lambda r: r["degrid_ms"])
     best = dict(grid=dict(wgs_per_cu=bg["wgs_per_cu"], max_chunk=bg["max_chunk"], waves=bg["waves"],
-                          variant=bg["variant"], ms=bg["grid_ms"], tiles=bg["tiles"]),
+                          variant=bg["variant"], planes=bg["planes"], ms=bg["grid_ms"], tiles=bg["tiles"]),
                 degrid=dict(wgs_per_cu=bd["wgs_per_cu"], max_chunk=bd["max_chunk"], waves=bd["waves"],
                             ms=bd["degrid_ms"], tiles=bd["tiles"]))
     # XCD grouping for the best grid shape: sum of grid and degrid time
@@ -176,7 +178,7 @@ def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2
     p = pg.plan(kg, uvw, max_chunk=bg["max_chunk"])
     best_x = (float("inf"), 1)
     for xg in (1, 2, 4, 8, 16, 32):
-        p.set_launch(bg["variant"], bg["waves"], bd["waves"], xg)
+        p.set_launch(bg["variant"], bg["waves"], bd["waves"], xg, bg["planes"])
         t = (_time(lambda: pg.grid(p, kg, vis, out=grid, fftshift=True), reps)
              + _time(lambda: pg.degrid(p, kd, grid, out=out, fftshift=True), reps))
         results.append(dict(xcd_group=xg, grid_plus_degrid_ms=t))
@@ -216,6 +218,7 @@ def main():
     ap.add_argument("--wgs", default="1,2,3,4", help="workgroups per CU to try")
     ap.add_argument("--waves", default="4,6,8,16", help="waves per workgroup to try")
     ap.add_argument("--chunks", default="256,1024", help="work item lengths to try")
+    ap.add_argument("--planes", default="0,2,1", help="output planes per gridder workgroup to try (0 = all)")
     ap.add_argument("--save", action="store_true")
     args = ap.parse_args()
     from . import polgrid as pg
@@ -229,7 +232,7 @@ def main():
     vis = torch.from_numpy(synth.random_vis(w.nvis, 4, np.random.default_rng(3))).cuda()
     ints = lambda t: tuple(int(v) for v in t.split(","))
     kw = dict(wgs=(1, 2, 4), waves=(4, 16), chunks=(256,)) if args.quick else dict(
-        wgs=ints(args.wgs), waves=ints(args.waves), chunks=ints(args.chunks))
+        wgs=ints(args.wgs), waves=ints(args.waves), chunks=ints(args.chunks), planes=ints(args.planes))
     best, results = tune(g, 4, jones, uvw, vis, w.eps_null, storage=args.storage, **kw)
     print("BEST", json.dumps(best), flush=True)
     if args.save:

@@ -352,14 +352,17 @@ int pg_plan_copy(const pg_plan* p, int32_t* perm, int32_t* fine, int32_t* items,
 void pg_plan_destroy(pg_plan* p) { delete p; }
 
 int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves,
-                       int32_t xcd_group) {
+                       int32_t xcd_group, int32_t grid_planes) {
   g_error.clear();
   if (!p) return fail(PG_EINVAL, "plan must be non-NULL");
   if (grid_variant < 0 || grid_variant > 2) return fail(PG_EINVAL, "grid_variant must be 0, 1 or 2");
   auto ok = [](int w) { return w == 4 || w == 6 || w == 8 || w == 16; };
   if (!ok(grid_waves) || !ok(degrid_waves)) return fail(PG_EINVAL, "waves per workgroup must be 4, 6, 8 or 16");
   if (xcd_group < 1 || xcd_group > 4096) return fail(PG_EINVAL, "xcd_group must be in [1, 4096]");
+  if (grid_planes != 0 && grid_planes != 1 && grid_planes != 2 && grid_planes != 4)
+    return fail(PG_EINVAL, "grid_planes must be 0, 1, 2 or 4");
   p->xcd_group = xcd_group;
+  p->grid_planes = grid_planes;
   p->grid_variant = grid_variant;
   p->grid_waves = grid_waves;
   p->degrid_waves = degrid_waves;

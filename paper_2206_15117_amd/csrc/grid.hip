@@ -226,14 +226,16 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(const Item* __restrict__
 // inside the wave's band [r0, r1), flattened to cnt = (b - a) S taps starting at tap t0, with the
 // row's visibility and kernel phase made wave-uniform (readlane of the lane that fetched them).
 // j < 0 gives an empty row.
-template <int NP, typename TapT>
+template <int NP, typename TapT, int NQ = NP>
 struct BandRow {
   int cnt = 0, a = 0, lx = 0;
   uint32_t t0 = 0;
   float2 v[NP];
-  TapChunks<NP * NP, TapT> tc;
+  TapChunks<NQ * NP, TapT> tc;
+  // q0: first of the NQ output planes this workgroup accumulates (Mueller rows q0 .. q0 + NQ - 1,
+  // which are chunks q0 NP / E .. of each phase block)
   __device__ BandRow(int j, int m_ly, int m_lx, int m_ph, int m_k, const float2* __restrict__ vis, int r0, int r1,
-                     int S, int SS, const TapT* plane_table)
+                     int S, int SS, const TapT* plane_table, int q0 = 0)
       : tc(plane_table, SS) {
     if (j < 0) {
 #pragma unroll
@@ -246,19 +248,19 @@ struct BandRow {
     t0 = static_cast<uint32_t>((a - ly) * S);
     lx = __builtin_amdgcn_readlane(m_lx, j);
     const int ph = __builtin_amdgcn_readlane(m_ph, j);
-    tc = TapChunks<NP * NP, TapT>(plane_table + static_cast<size_t>(ph) * SS * NP * NP, SS);
+    tc = TapChunks<NQ * NP, TapT>(plane_table + (static_cast<size_t>(ph) * NP * NP + q0 * NP) * SS, SS);
     const int k = __builtin_amdgcn_readlane(m_k, j);  // uniform: the row's values come in by scalar loads
 #pragma unroll
     for (int c = 0; c < NP; ++c) v[c] = vis[static_cast<size_t>(k) * NP + c];
   }
   // Adds the Mueller product of one tap into the LDS sub-grid at element off of each Stokes plane
   // (planes WP apart): all npol reads are issued before the arithmetic and all writes after it.
-  __device__ __forceinline__ void apply(float2* lds, int off, const float2 (&tap)[NP * NP], int WP) const {
-    float2 g[NP];
+  __device__ __forceinline__ void apply(float2* lds, int off, const float2 (&tap)[NQ * NP], int WP) const {
+    float2 g[NQ];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) g[q] = lds[q * WP + off];
+    for (int q = 0; q < NQ; ++q) g[q] = lds[q * WP + off];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
+    for (int q = 0; q < NQ; ++q) {
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
         const float2 t2 = tap[q * NP + c];
@@ -267,7 +269,7 @@ struct BandRow {
       }
     }
 #pragma unroll
-    for (int q = 0; q < NP; ++q) lds[q * WP + off] = g[q];
+    for (int q = 0; q < NQ; ++q) lds[q * WP + off] = g[q];
   }
 };
 
@@ -275,19 +277,19 @@ struct BandRow {
 // weighted by how many footprints of the item cover them); wave w owns band w and walks every
 // visibility of the item, taking only the footprint rows inside its band.  Bands are disjoint, so
 // the sub-grid (complex [q][W][P] in LDS) is updated with plain read-modify-write, no LDS atomics.
-template <int NP, typename TapT, int NW, bool PAIR>
+template <int NP, typename TapT, int NW, bool PAIR, int NQ = NP>
 __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __restrict__ fine,
                                                  const int32_t* __restrict__ perm, const float2* __restrict__ vis,
                                                  const TapT* __restrict__ table, const PlaneInfo* __restrict__ planes,
                                                  int os, int n, float2* __restrict__ grid, int flags, int sub_bytes,
-                                                 float* lds_f) {
+                                                 float* lds_f, int q0 = 0) {
   float2* lds = reinterpret_cast<float2*>(lds_f);
   int* rowload = reinterpret_cast<int*>(reinterpret_cast<char*>(lds_f) + sub_bytes);  // [W + 1]
   int* band = rowload + 256;                                                             // [NW + 1]
   const PlaneInfo pl = planes[it.plane];
   const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
   const float inv_s = 1.0f / static_cast<float>(S);
-  for (int i = threadIdx.x; i < NP * WP; i += (NW * 64)) lds[i] = make_float2(0.0f, 0.0f);
+  for (int i = threadIdx.x; i < NQ * WP; i += (NW * 64)) lds[i] = make_float2(0.0f, 0.0f);
   for (int i = threadIdx.x; i <= W; i += (NW * 64)) rowload[i] = 0;
   __syncthreads();
   // coverage count of every sub-grid row (difference array, then a prefix sum in one wave)
@@ -382,10 +384,10 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
         }
         jb = __builtin_amdgcn_readfirstlane(jb);
       }
-      const BandRow<NP, TapT> ra(ja, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset);
-      const BandRow<NP, TapT> rb(jb, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset);
-      constexpr uint32_t TB = TapChunks<NP * NP, TapT>::kTapBytes;
-      float2 ta[NP * NP], tb[NP * NP];
+      const BandRow<NP, TapT, NQ> ra(ja, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset, q0);
+      const BandRow<NP, TapT, NQ> rb(jb, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset, q0);
+      constexpr uint32_t TB = TapChunks<NQ * NP, TapT>::kTapBytes;
+      float2 ta[NQ * NP], tb[NQ * NP];
       const bool la = lane < ra.cnt, lb = lane < rb.cnt;
       uint32_t ba = (ra.t0 + static_cast<uint32_t>(lane)) * TB, bb = (rb.t0 + static_cast<uint32_t>(lane)) * TB;
       if (la) ra.tc.load_at(ba, ta);
@@ -394,7 +396,7 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
       if (la) ra.apply(lds, ca.off, ta, WP);
 #pragma unroll 1
       for (int u = lane + 64; u < ra.cnt; u += 64) {
-        float2 t[NP * NP];
+        float2 t[NQ * NP];
         ba += 64 * TB;
         ra.tc.load_at(ba, t);
         ca.advance(step);
@@ -404,7 +406,7 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
       if (lb) rb.apply(lds, cb.off, tb, WP);
 #pragma unroll 1
       for (int u = lane + 64; u < rb.cnt; u += 64) {
-        float2 t[NP * NP];
+        float2 t[NQ * NP];
         bb += 64 * TB;
         rb.tc.load_at(bb, t);
         cb.advance(step);
@@ -422,10 +424,10 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
     const int l = y * P + x;
     const float sg = (shift && ((X + Y) & 1)) ? -1.0f : 1.0f;
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const float2 g = lds[q * WP + l];
       if (g.x != 0.0f || g.y != 0.0f) {
-        float* gp = reinterpret_cast<float*>(grid + q * pstride + static_cast<size_t>(Y) * n + X);
+        float* gp = reinterpret_cast<float*>(grid + (q0 + q) * pstride + static_cast<size_t>(Y) * n + X);
         unsafeAtomicAdd(gp, sg * g.x);
         unsafeAtomicAdd(gp + 1, sg * g.y);
       }
@@ -433,7 +435,7 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
   }
 }
 
-template <int NP, typename TapT, int NW>
+template <int NP, typename TapT, int NW, int NQ = NP>
 __global__ __launch_bounds__(NW * 64) void grid_banded_kernel(const Item* __restrict__ items,
                                                               const int2* __restrict__ fine,
                                                               const int32_t* __restrict__ perm,
@@ -443,11 +445,13 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_kernel(const Item* __rest
                                                               float2* __restrict__ grid, int flags, int sub_bytes,
                                                               int n_items, int group) {
   extern __shared__ float lds_f[];
-  const int item = xcd_item(blockIdx.x, group);
+  // NP / NQ workgroups per item, each accumulating NQ of the output planes
+  const int w = xcd_item(blockIdx.x, group);
+  const int item = w / (NP / NQ), part = w - item * (NP / NQ);
   if (item >= n_items) return;
   // two rows in flight costs registers: 1024-thread workgroups (capped at 128) take one at a time
-  grid_item_banded<NP, TapT, NW, (NW <= 8)>(items[item], fine, perm, vis, table, planes, os, n, grid, flags,
-                                            sub_bytes, lds_f);
+  grid_item_banded<NP, TapT, NW, (NW <= 8), NQ>(items[item], fine, perm, vis, table, planes, os, n, grid, flags,
+                                                sub_bytes, lds_f, part * NQ);
 }
 
 // The batch field table is read through the constant address space: the compiler then takes the
@@ -634,18 +638,32 @@ hipError_t allow_lds(F* fn, size_t bytes) {
                              static_cast<int>(bytes));
 }
 
-template <int NP, typename TapT, int NW>
+template <int NP, typename TapT, int NW, int NQ = NP>
 hipError_t run_grid_banded(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
                            hipStream_t s) {
-  auto fn = grid_banded_kernel<NP, TapT, NW>;
-  const size_t bytes = k->lds_bytes + kBandScratch;
+  auto fn = grid_banded_kernel<NP, TapT, NW, NQ>;
+  const size_t sub = k->lds_bytes / NP * NQ;
+  const size_t bytes = sub + kBandScratch;
   hipError_t e = allow_lds(fn, bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(xcd_blocks(p->n_items, p->xcd_group)), dim3(NW * 64), bytes, s, p->items.as<Item>(),
-                     p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(), k->planes.as<PlaneInfo>(),
-                     k->os, k->n, grid, flags, static_cast<int>(k->lds_bytes), static_cast<int>(p->n_items),
-                     p->xcd_group);
+  hipLaunchKernelGGL(fn, dim3(xcd_blocks(p->n_items * (NP / NQ), p->xcd_group)), dim3(NW * 64), bytes, s,
+                     p->items.as<Item>(), p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(),
+                     k->planes.as<PlaneInfo>(), k->os, k->n, grid, flags, static_cast<int>(sub),
+                     static_cast<int>(p->n_items), p->xcd_group);
   return hipGetLastError();
+}
+
+// Output planes per workgroup (the plan's grid_planes; 0 or npol: all).  With fewer, NP / NQ
+// workgroups share each work item, each accumulating NQ planes from its NQ rows of the Mueller
+// kernels: the sub-grid in LDS shrinks by NP / NQ, so more workgroups fit on a CU.
+template <int NP, typename TapT, int NW>
+hipError_t run_grid_banded_planes(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
+                                  hipStream_t s) {
+  if constexpr (NP == 4) {
+    if (p->grid_planes == 2) return run_grid_banded<NP, TapT, NW, 2>(p, k, vis, grid, flags, s);
+    if (p->grid_planes == 1) return run_grid_banded<NP, TapT, NW, 1>(p, k, vis, grid, flags, s);
+  }
+  return run_grid_banded<NP, TapT, NW>(p, k, vis, grid, flags, s);
 }
 
 template <int NP, typename TapT>
@@ -660,10 +678,10 @@ hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, fl
   if (flags & PG_VARIANT_BANDED) banded = true;
   if (banded) {
     switch (p->grid_waves) {
-      case 4: return run_grid_banded<NP, TapT, 4>(p, k, vis, grid, flags, s);
-      case 6: return run_grid_banded<NP, TapT, 6>(p, k, vis, grid, flags, s);
-      case 8: return run_grid_banded<NP, TapT, 8>(p, k, vis, grid, flags, s);
-      default: return run_grid_banded<NP, TapT, 16>(p, k, vis, grid, flags, s);
+      case 4: return run_grid_banded_planes<NP, TapT, 4>(p, k, vis, grid, flags, s);
+      case 6: return run_grid_banded_planes<NP, TapT, 6>(p, k, vis, grid, flags, s);
+      case 8: return run_grid_banded_planes<NP, TapT, 8>(p, k, vis, grid, flags, s);
+      default: return run_grid_banded_planes<NP, TapT, 16>(p, k, vis, grid, flags, s);
     }
   }
   auto fn = grid_kernel<NP, TapT>;

@@ -220,6 +220,24 @@ def test_c2_launch_shapes(c2_case, waves, group):
     assert rel(gv, gridding.degrid(w.geom, td, w.uvw, g)) < TOL
 
 
+@pytest.mark.parametrize("planes,waves,group", [(1, 4, 1), (1, 8, 3), (2, 4, 2), (2, 16, 1), (4, 6, 5), (1, 16, 64)])
+def test_c2_grid_output_plane_split(c2_case, planes, waves, group):
+    """Work items shared by 4 / planes workgroups, each accumulating `planes` of the four output
+    correlations from its rows of the Mueller kernels, give the oracle grid; float16 tables too
+    (against the oracle on the rounded table)."""
+    w, vis, tg, _, kg, _ = c2_case
+    p = pg.plan(kg, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves, group, planes)
+    got = host(pg.grid(p, kg, dev(vis)))
+    want = gridding.grid(w.geom, tg, w.uvw, vis)
+    for q in range(4):
+        assert rel(got[q], want[q]) < TOL, (planes, q)
+    if planes == 1 and waves == 4:
+        k16 = gpu_kernels(w, pg.KIND_GRID, storage=pg.STORE_F16)
+        p16 = pg.plan(k16, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves, group, planes)
+        got = host(pg.grid(p16, k16, dev(vis)))
+        assert rel(got, gridding.grid(w.geom, kernels.round_tables(tg, np.float16), w.uvw, vis)) < TOL
+
+
 def test_c2_degrid_parity(c2_case):
     w, _, _, td, _, kd = c2_case
     rng = np.random.default_rng(4)
