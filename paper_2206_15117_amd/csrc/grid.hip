@@ -137,6 +137,24 @@ struct TapCursor {
   }
 };
 
+// Sum over the 64 lanes of a wave, left in lane 63, with DPP lane moves folded into the adds:
+// pairs and quads (quad permutes), rows of 16 (rotations by 4 and 8), then the row broadcasts of
+// lanes 15 and 31 into the rows above.  Vector ALU only; a shuffle through LDS would cost one LDS
+// round trip per step.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += dpp_move<0xb1>(v);        // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4e>(v);        // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x124>(v);       // row_ror 4
+  v += dpp_move<0x128>(v);       // row_ror 8: every lane of a row holds the row's sum
+  v += dpp_move<0x142, 0xa>(v);  // row_bcast 15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);  // row_bcast 31 into rows 2 and 3
+  return v;
+}
+
 // Workgroup -> work item map that keeps `group` consecutive items (one plane, neighbouring tiles,
 // so the same kernel-table rows and overlapping sub-grid halos) on one XCD and its L2.  The
 // hardware hands workgroups to the 8 XCDs round-robin (block b to XCD b mod 8), so block b =
@@ -554,10 +572,8 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
         }
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int c = 0; c < 2 * NP; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
-      if (lane == 0) {
+      for (int c = 0; c < 2 * NP; ++c) acc[c] = wave_sum_to_lane63(acc[c]);
+      if (lane == 63) {
 #pragma unroll
         for (int c = 0; c < NP; ++c)
           if (flags & PG_ACCUMULATE) {
