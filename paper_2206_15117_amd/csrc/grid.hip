@@ -501,6 +501,68 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_batch(const FieldArgs* __
                                             flags, sub_bytes, lds_f);
 }
 
+// R consecutive rows of a work item that share one kernel phase (rows are phase-sorted inside a
+// tile), degridded together: every tap is loaded once and applied to all R rows, whose sub-grid
+// positions differ by a wave-uniform offset.  One 64-lane sum per row and output value; lane 63
+// writes the rows' visibilities.
+template <int NP, typename TapT, int R>
+__device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase_table, int j, int m_ly, int m_lx,
+                                            int m_k, int S, int SS, int P, int WP, float inv_s,
+                                            const FootStep& step, float2* __restrict__ vis_out, int flags,
+                                            int lane) {
+  const TapChunks<NP * NP, TapT> tc(phase_table, SS);
+  const int ly0 = __builtin_amdgcn_readlane(m_ly, j), lx0 = __builtin_amdgcn_readlane(m_lx, j);
+  int d[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    d[r] = (__builtin_amdgcn_readlane(m_ly, j + r) - ly0) * P + (__builtin_amdgcn_readlane(m_lx, j + r) - lx0);
+  float acc[R][2 * NP];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < 2 * NP; ++c) acc[r][c] = 0.0f;
+  constexpr uint32_t TB = TapChunks<NP * NP, TapT>::kTapBytes;
+  TapCursor cur(lane, ly0, lx0, inv_s, S, P);
+  uint32_t boff = static_cast<uint32_t>(lane) * TB;
+#pragma unroll(R == 1 ? 2 : 1)
+  for (int t = lane; t < SS; t += 64) {
+    float2 tap[NP * NP];
+    tc.load_at(boff, tap);
+    const int off = cur.off;
+    boff += 64 * TB;
+    cur.advance(step);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const float2 g = lds[q * WP + off + d[r]];
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+          const float2 a = tap[q * NP + c];  // conj(a) * g
+          acc[r][2 * c] = fmaf(a.x, g.x, fmaf(a.y, g.y, acc[r][2 * c]));
+          acc[r][2 * c + 1] = fmaf(a.x, g.y, fmaf(-a.y, g.x, acc[r][2 * c + 1]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int c = 0; c < 2 * NP; ++c) acc[r][c] = wave_sum_to_lane63(acc[r][c]);
+    const int k = __builtin_amdgcn_readlane(m_k, j + r);
+    if (lane == 63) {
+#pragma unroll
+      for (int c = 0; c < NP; ++c)
+        if (flags & PG_ACCUMULATE) {
+          float2& o = vis_out[static_cast<size_t>(k) * NP + c];
+          o = make_float2(o.x + acc[r][2 * c], o.y + acc[r][2 * c + 1]);
+        } else {
+          vis_out[static_cast<size_t>(k) * NP + c] = make_float2(acc[r][2 * c], acc[r][2 * c + 1]);
+        }
+    }
+  }
+}
+
 template <int NP, typename TapT, int NW>
 __device__ __forceinline__ void degrid_item(const Item it, const int2* __restrict__ fine,
                                             const int32_t* __restrict__ perm, const TapT* __restrict__ table,
@@ -527,12 +589,14 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const FootStep step(S, P);
-  // wave w takes rows start + w, start + w + NW, ...; metadata of 64 of them at a time comes in one
-  // coalesced load and is broadcast per row with readlane
-  for (int blk = it.start + wave; blk < it.end; blk += 64 * NW) {
-    const int mine = blk + lane * NW;
-    int m_ly = 0, m_lx = 0, m_ph = 0, m_k = 0;
-    if (mine < it.end) {
+  // wave w takes a contiguous run of the item's rows, so rows of one phase stay together; their
+  // metadata comes in 64 at a time by one coalesced load and is broadcast per row with readlane
+  const int per = (it.end - it.start + NW - 1) / NW;
+  const int w0 = it.start + wave * per, w1 = min(it.end, w0 + per);
+  for (int blk = w0; blk < w1; blk += 64) {
+    const int mine = blk + lane;
+    int m_ly = 0, m_lx = 0, m_ph = -1, m_k = 0;
+    if (mine < w1) {
       const int2 f = fine[mine];
       const int x0 = ceil_div_i(f.x - half + 1, os), y0 = ceil_div_i(f.y - half + 1, os);
       m_ly = y0 - it.oy;
@@ -540,49 +604,22 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
       m_ph = (y0 * os - f.y + half - 1) * os + (x0 * os - f.x + half - 1);
       m_k = perm[mine];
     }
-    const int nrow = min(64, (it.end - blk + NW - 1) / NW);
-    for (int j = 0; j < nrow; ++j) {
-      const int ly = __builtin_amdgcn_readlane(m_ly, j);
-      const int lx = __builtin_amdgcn_readlane(m_lx, j);
+    const int nrow = min(64, w1 - blk);
+    for (int j = 0; j < nrow;) {
       const int ph = __builtin_amdgcn_readlane(m_ph, j);
-      const int k = __builtin_amdgcn_readlane(m_k, j);
-      const TapChunks<NP * NP, TapT> tc(table + pl.offset + static_cast<size_t>(ph) * SS * NP * NP, SS);
-      float acc[2 * NP];
-#pragma unroll
-      for (int c = 0; c < 2 * NP; ++c) acc[c] = 0.0f;
-      constexpr uint32_t TB = TapChunks<NP * NP, TapT>::kTapBytes;
-      TapCursor cur(lane, ly, lx, inv_s, S, P);
-      uint32_t boff = static_cast<uint32_t>(lane) * TB;
-#pragma unroll 2
-      for (int t = lane; t < SS; t += 64) {
-        float2 tap[NP * NP];
-        tc.load_at(boff, tap);
-        const int off = cur.off;
-        boff += 64 * TB;
-        cur.advance(step);
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          const float2 g = lds[q * WP + off];
-#pragma unroll
-          for (int c = 0; c < NP; ++c) {
-            const float2 a = tap[q * NP + c];  // conj(a) * g
-            acc[2 * c] = fmaf(a.x, g.x, fmaf(a.y, g.y, acc[2 * c]));
-            acc[2 * c + 1] = fmaf(a.x, g.y, fmaf(-a.y, g.x, acc[2 * c + 1]));
-          }
-        }
+      int run = 1;  // rows from j on with the same phase, up to 4
+      while (run < 4 && j + run < nrow && __builtin_amdgcn_readlane(m_ph, j + run) == ph) ++run;
+      run = __builtin_amdgcn_readfirstlane(run);
+      const TapT* pt = table + pl.offset + static_cast<size_t>(ph) * SS * NP * NP;
+      if (run == 4) {
+        degrid_rows<NP, TapT, 4>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane);
+      } else if (run >= 2) {
+        degrid_rows<NP, TapT, 2>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane);
+        run = 2;
+      } else {
+        degrid_rows<NP, TapT, 1>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane);
       }
-#pragma unroll
-      for (int c = 0; c < 2 * NP; ++c) acc[c] = wave_sum_to_lane63(acc[c]);
-      if (lane == 63) {
-#pragma unroll
-        for (int c = 0; c < NP; ++c)
-          if (flags & PG_ACCUMULATE) {
-            float2& o = vis_out[static_cast<size_t>(k) * NP + c];
-            o = make_float2(o.x + acc[2 * c], o.y + acc[2 * c + 1]);
-          } else {
-            vis_out[static_cast<size_t>(k) * NP + c] = make_float2(acc[2 * c], acc[2 * c + 1]);
-          }
-      }
+      j += run;
     }
   }
 }
