@@ -317,7 +317,7 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
     atomicAdd(&rowload[ly + S], -1);
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (wave == 0) {
     int carry = 0;
     for (int r0 = 0; r0 < W; r0 += 64) {  // inclusive prefix sums: coverage, then cumulative load
@@ -361,7 +361,9 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
     }
   }
   __syncthreads();
-  const int r0 = band[wave], r1 = band[wave + 1];
+  // band bounds are the same for the whole wave: scalar registers, so the row walk below (band
+  // tests, row bounds) runs on the scalar unit instead of the vector ALU
+  const int r0 = __builtin_amdgcn_readfirstlane(band[wave]), r1 = __builtin_amdgcn_readfirstlane(band[wave + 1]);
   const FootStep step(S, P);
   // Metadata of 64 rows is fetched lane-parallel in one coalesced load and broadcast per row with
   // readlane, so walking the item costs one memory latency per 64 rows, not two per row.
@@ -587,7 +589,7 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
     }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const FootStep step(S, P);
   // wave w takes a contiguous run of the item's rows, so rows of one phase stay together; their
   // metadata comes in 64 at a time by one coalesced load and is broadcast per row with readlane
