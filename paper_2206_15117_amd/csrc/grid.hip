@@ -378,31 +378,21 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
       m_ph = (y0 * os - f.y + half - 1) * os + (x0 * os - f.x + half - 1);
       m_k = perm[mine];
     }
-    const int nrow = min(64, it.end - blk);
+    // The rows of this block whose footprint meets the wave's band, as one 64-bit mask (each lane
+    // tests its own row), walked in order with find-first-set on the scalar unit.
     // With PAIR, rows are taken two at a time: the first 64 taps of both are requested before either
     // is applied, so one memory latency covers two rows.  LDS updates stay in row order (a wave's LDS
     // operations execute in program order), so overlapping footprints need no synchronisation.
-    int j = 0;
-    for (;;) {
-      int ja = -1, jb = -1;
-      for (; j < nrow; ++j) {
-        const int ly = __builtin_amdgcn_readlane(m_ly, j);
-        if (max(ly, r0) < min(ly + S, r1)) {
-          ja = j++;
-          break;
-        }
-      }
-      ja = __builtin_amdgcn_readfirstlane(ja);  // row indices are wave-uniform: keep them scalar
-      if (ja < 0) break;
+    uint64_t hits = __ballot(mine < it.end && max(m_ly, r0) < min(m_ly + S, r1));
+    while (hits) {
+      const int ja = __builtin_ctzll(hits);
+      hits &= hits - 1;
+      int jb = -1;
       if constexpr (PAIR) {
-        for (; j < nrow; ++j) {
-          const int ly = __builtin_amdgcn_readlane(m_ly, j);
-          if (max(ly, r0) < min(ly + S, r1)) {
-            jb = j++;
-            break;
-          }
+        if (hits) {
+          jb = __builtin_ctzll(hits);
+          hits &= hits - 1;
         }
-        jb = __builtin_amdgcn_readfirstlane(jb);
       }
       const BandRow<NP, TapT, NQ> ra(ja, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset, q0);
       const BandRow<NP, TapT, NQ> rb(jb, m_ly, m_lx, m_ph, m_k, vis, r0, r1, S, SS, table + pl.offset, q0);
