@@ -1,21 +1,25 @@
 // Gridding, degridding and taper correction on gfx950.
 //
 // Gridding (Sec. 3.2, gridding stage) and degridding (Sec. 3.2, degridding
-// stage) with 4x4 Mueller kernels.  One workgroup takes one work item: a chunk
-// of visibilities that share a w-plane and a uv tile (binned by the plan,
-// phase-sorted inside the tile so neighbouring visibilities reuse table lines
-// in cache).  The tile's sub-grid of (T + S - 1)^2 points x npol lives in LDS
-// with a row pitch congruent to S modulo 32 complex elements, so the 64 lanes of
-// a wave, which walk consecutive taps of one visibility across footprint rows,
-// hit distinct banks.  Table taps are stored chunk-major per phase
-// ([chunk][tap][e]), so each 16-byte load of 64 consecutive taps is one
-// contiguous 1 KiB block.
-//   grid:   each wave takes one visibility at a time; lane t owns tap t; the
-//           npol x npol Mueller product is done in registers and added into
-//           the LDS sub-grid with LDS float atomics (waves overlap); the
-//           sub-grid is flushed with coalesced global float atomics.
-//   degrid: the sub-grid is loaded once into LDS; each wave reduces one
-//           visibility's taps with cross-lane shuffles.
+// stage) with 4x4 Mueller kernels.  A work item is a chunk of visibilities that
+// share a w-plane and a uv tile (binned by the plan, phase-sorted inside the
+// tile so neighbouring visibilities reuse table lines in cache).  The tile's
+// sub-grid of (T + S - 1)^2 points lives in LDS with a row pitch congruent to S
+// modulo 32 complex elements, so the 64 lanes of a wave, which walk consecutive
+// taps of one visibility across footprint rows, hit distinct banks.  Table taps
+// are stored chunk-major per phase ([chunk][tap][e]), so each 16-byte load of 64
+// consecutive taps is one contiguous 1 KiB block.
+//   grid (row bands): the sub-grid rows are split into one band of equal load
+//           per wave; each wave walks the item's visibilities and applies the
+//           footprint rows inside its band with plain LDS read-modify-write
+//           (bands are disjoint); one to four workgroups share an item, each
+//           accumulating its share of the output correlations; the sub-grid is
+//           flushed with coalesced global float atomics.
+//   grid (LDS atomics): each wave takes whole visibilities and adds into the
+//           sub-grid with LDS float atomics (narrow sub-grids only).
+//   degrid: the sub-grid is loaded once into LDS; each wave takes a run of the
+//           item's visibilities, degrids same-phase neighbours together and
+//           reduces each visibility's taps across the wave.
 #include "common.hpp"
 
 namespace pg {
