@@ -14,6 +14,7 @@ Prints one JSON line.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -43,6 +44,7 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-kernel section")
     ap.add_argument("--no-scale", action="store_true", help="skip the 20M-row major-cycle section")
     ap.add_argument("--no-clean", action="store_true", help="skip the Cotton-Schwab clean section")
+    ap.add_argument("--no-mosaic", action="store_true", help="skip the 7-field mosaic section")
     ap.add_argument("--surrogate-kernels", type=int, default=200_000,
                     help="teacher kernels the network is trained on")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -217,6 +219,10 @@ def main():
         torch.cuda.empty_cache()
         out["scale"] = bench_scale(2, 1)
         log(f"major-cycle step timed: {out['scale']['ms_per_step']:.1f} ms")
+    if not args.no_mosaic:
+        torch.cuda.empty_cache()
+        out["mosaic"] = bench_mosaic(2, 1)
+        log(f"mosaic step timed: {out['mosaic']['ms_per_step']:.1f} ms")
     if not args.no_surrogate:
         torch.cuda.empty_cache()
         out["surrogate"] = bench_surrogate(args.surrogate_kernels)
@@ -427,6 +433,120 @@ def bench_scale(steps, warmup):
             "ms_per_step": 1e3 * wall, "breakdown_ms": ms, "make_kernels_s": t_kernels,
             "grid_tflops": 128.0 * s2 / (ms["grid"] * 1e-3) / 1e12,
             "rows_per_s_grid_plus_degrid": w.nvis / ((ms["grid"] + ms["degrid"]) * 1e-3)}
+
+
+def bench_mosaic(steps, warmup):
+    """The major cycle as a 7-field image-domain mosaic (Sec. 2.2): config 5's 20M rows in seven
+    fields, each imaged on its own 8192^2 x 4 frame about its pointing (plan -> grid -> FFT ->
+    taper) and reprojected, weighted by its squared power beam inside the eps = 0.2 mask, onto a
+    10240^2 mosaic frame; normalisation; then the mosaic reprojected back onto every field and
+    predicted (taper -> inverse FFT -> degrid).  Input visibilities: a 1000-component model
+    placed on the mosaic frame and predicted through the same path."""
+    import torch
+
+    import synth
+    from paper_2206_15117_amd import autotune
+    from paper_2206_15117_amd import mosaic as mos
+    from paper_2206_15117_amd import polgrid as pg
+
+    w, centres, mf = synth.config5_mosaic()
+    launch = autotune.apply(w.geom, 4, pg.STORE_F32)
+    g = launch.geom
+    jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
+    kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=w.eps_null)
+    kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones)
+    n, nf = g.n, len(centres)
+    mframe = mos.SkyFrame(*mf)
+    frames = [mos.SkyFrame(n, g.cell, ra, dec) for ra, dec in centres]
+    bounds = np.linspace(0, w.nvis, nf + 1).astype(np.int64)
+    uvws = [torch.from_numpy(np.ascontiguousarray(w.uvw[a:b])).cuda() for a, b in zip(bounds[:-1], bounds[1:])]
+    # the same weight image in every field's own frame: squared power beam (FWHM 1 deg) where
+    # the power beam is at least 0.2 of its peak
+    x = (torch.arange(n, device="cuda", dtype=torch.float64) - n // 2) * g.cell
+    pb = torch.exp(-4.0 * math.log(2.0) * (x[None, :] ** 2 + x[:, None] ** 2) / (1.0 * synth.DEG) ** 2)
+    wimg = torch.where(pb >= 0.2, pb * pb, torch.zeros_like(pb)).float().contiguous()
+    del x, pb
+    plans = [autotune.plan(kg, u, launch) for u in uvws]
+    fields = [mos.Field(fr, p, kg, kd, wimg, float(p.n_kept)) for fr, p in zip(frames, plans)]
+    model = torch.zeros((4, mframe.n, mframe.n), dtype=torch.float32, device="cuda")
+    jj = np.clip(np.round(w.src_l / g.cell).astype(int) + mframe.n // 2, 0, mframe.n - 1)
+    ii = np.clip(np.round(w.src_m / g.cell).astype(int) + mframe.n // 2, 0, mframe.n - 1)
+    idx = torch.from_numpy((ii * mframe.n + jj).astype(np.int64)).cuda()
+    for q in range(4):
+        model[q].view(-1).index_add_(0, idx, torch.from_numpy(w.src_iquv[:, q].astype(np.float32)).cuda())
+    vis = mos.predict(fields, model, mframe)
+    del model
+    log("mosaic inputs predicted")
+    grid_buf = torch.empty((4, n, n), dtype=torch.complex64, device="cuda")
+    pbuf = torch.empty_like(grid_buf)
+    img = torch.empty((4, n, n), dtype=torch.float32, device="cuda")
+    mimg = torch.empty((4, mframe.n, mframe.n), dtype=torch.float32, device="cuda")
+    mw = torch.empty((mframe.n, mframe.n), dtype=torch.float32, device="cuda")
+    vis_out = [torch.empty_like(v) for v in vis]
+    stages = ("plan", "grid", "fft_taper", "reproject_to_mosaic", "normalise", "reproject_to_field", "predict")
+    ev = {k: [] for k in stages}
+
+    def mark(rec, k, a, b):
+        if rec:
+            ev[k].append((a, b))
+
+    def ev_now():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def step(rec):
+        mimg.zero_()
+        mw.zero_()
+        for f in range(nf):
+            e0 = ev_now()
+            p = autotune.plan(kg, uvws[f], launch)
+            e1 = ev_now()
+            pg.grid(p, kg, vis[f], out=grid_buf, fftshift=True)
+            e2 = ev_now()
+            pg.taper(kg, torch.fft.fft2(grid_buf), img, pg.TAPER_IMAGE, float(p.n_kept))
+            e3 = ev_now()
+            pg.reproject(img, frames[f], mimg, mframe, src_weight=wimg, dst_weight=mw, accumulate=True)
+            e4 = ev_now()
+            fields[f].plan = p
+            for k, a, b in (("plan", e0, e1), ("grid", e1, e2), ("fft_taper", e2, e3), ("reproject_to_mosaic", e3, e4)):
+                mark(rec, k, a, b)
+        e0 = ev_now()
+        pg.weight_normalise(mimg, mw, 1e-3)
+        mark(rec, "normalise", e0, ev_now())
+        for f in range(nf):
+            e0 = ev_now()
+            pg.reproject(mimg, mframe, img, frames[f])
+            e1 = ev_now()
+            pg.taper(kd, img, pbuf, pg.TAPER_PREDICT)
+            pg.degrid(fields[f].plan, kd, torch.fft.ifft2(pbuf, norm="forward"), out=vis_out[f], fftshift=True)
+            e2 = ev_now()
+            mark(rec, "reproject_to_field", e0, e1)
+            mark(rec, "predict", e1, e2)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = {k: float(sum(a.elapsed_time(b) for a, b in v) / steps) for k, v in ev.items()}
+    # reprojection roofline: algorithmic HBM bytes per destination pixel (each source value read
+    # once, destination and weight read-modified-written): to the mosaic 4 x (4 + 8) + 4 + 8 B,
+    # to a field 4 x (4 + 4) B
+    b_mos = nf * mframe.n ** 2 * (4 * 12 + 12)
+    b_fld = nf * n * n * 4 * 8
+    rep_gbs = (b_mos + b_fld) / ((ms["reproject_to_mosaic"] + ms["reproject_to_field"]) * 1e-3) / 1e9
+    return {"workload": f"7-field image-domain mosaic of the major cycle: {nf} fields x {n}x{n}x4 (own phase centres, "
+                        f"hexagon at 0.5 deg), mosaic frame {mframe.n}x{mframe.n}x4, {w.nvis} rows in total, "
+                        f"{g.nplanes} w-planes",
+            "rows": w.nvis, "fields": nf, "value": w.nvis / wall, "unit": "vis/s", "ms_per_step": 1e3 * wall,
+            "breakdown_ms": ms,
+            "reproject_roofline": {"bound": "hbm", "achieved": rep_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": rep_gbs / HBM_PEAK_GBS,
+                                   "bytes_per_step": b_mos + b_fld}}
 
 
 def bench_surrogate(n_kernels):

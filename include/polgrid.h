@@ -317,6 +317,37 @@ void pg_batch_destroy(pg_batch* b);
 int pg_taper(const pg_kernels* k, const void* in, void* out, int32_t direction, double weight_sum,
              void* stream);
 
+/* ------------------------------------------------------------------ image-domain mosaics
+ * Sec. 2.2: each mosaic field is imaged at its own phase centre and image-plane reprojection
+ * builds the mosaic at a common phase centre; before degridding, the model is reprojected back
+ * to each field's phase centre.  A sky frame is an n x n orthographic (SIN) projection about
+ * (ra, dec) (radians) with pixel (row i, column j) at direction cosines l = (j - n/2) cell,
+ * m = (i - n/2) cell, where l = cos d sin(a - ra), m = sin d cos(dec) - cos d sin(dec) cos(a - ra). */
+typedef struct pg_sky_frame {
+  int32_t n;   /* pixels per side, 2 .. 65536 */
+  double cell; /* radians per pixel, > 0 */
+  double ra;   /* phase centre, radians (finite) */
+  double dec;  /* phase centre, radians, |dec| <= pi/2 */
+} pg_sky_frame;
+
+/* Reprojection: for every destination pixel, its direction is mapped into the source frame at
+ * pixel position (x, y) (x = column), computed in float64.  The pixel is covered when the
+ * direction is in front of both phase centres and -1e-6 <= x, y <= n_src - 1 + 1e-6 (positions
+ * then clamped to [0, n_src - 1]); s_q = bilinear sample of src plane q at (x, y) and
+ * w = bilinear sample of src_weight (1 if src_weight is NULL); uncovered: s_q = 0, w = 0.
+ *   flags 0:             dst[q] = s_q,        dst_weight = w   (if dst_weight is non-NULL)
+ *   flags PG_ACCUMULATE: dst[q] += w s_q,     dst_weight += w
+ * src float32 [npol][n_src][n_src], src_weight float32 [n_src][n_src] or NULL, dst float32
+ * [npol][n_dst][n_dst], dst_weight float32 [n_dst][n_dst] or NULL; all device memory, the
+ * caller's; src and dst must not overlap.  npol 1..4.  Enqueue only.  Errors: PG_EINVAL. */
+int pg_reproject(const float* src, const float* src_weight, const pg_sky_frame* src_frame, float* dst,
+                 float* dst_weight, const pg_sky_frame* dst_frame, int32_t npol, int32_t flags, void* stream);
+
+/* Mosaic normalisation: img[q][p] = img[q][p] / weight[p] where weight[p] >= min_weight, else 0
+ * (the weighted mean of the fields accumulated by pg_reproject).  img float32 [npol][n][n],
+ * weight float32 [n][n], device memory.  min_weight > 0.  Enqueue only.  Errors: PG_EINVAL. */
+int pg_weight_normalise(float* img, const float* weight, int32_t n, int32_t npol, float min_weight, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

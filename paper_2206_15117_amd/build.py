@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libpolgrid.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "pswf.cpp", "mueller.cpp", "kernels_gen.hip", "plan.hip", "grid.hip", "mlp.hip",
-           "mlp_api.cpp", "clean.hip"]
+           "mlp_api.cpp", "clean.hip", "mosaic.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "mosaic.hpp"
 
 namespace pg {
 
@@ -518,6 +519,43 @@ int pg_taper(const pg_kernels* k, const void* in, void* out, int32_t direction, 
     return fail(PG_EINVAL, "weight_sum must be positive and finite");
   if (direction == PG_TAPER_PREDICT && !is_finite(weight_sum)) return fail(PG_EINVAL, "scale must be finite");
   PG_HIP(launch_taper(k, in, out, direction, weight_sum, static_cast<hipStream_t>(stream)), "taper");
+  return PG_OK;
+}
+
+namespace {
+int check_frame(const pg_sky_frame* f, const char* what) {
+  if (!f) return fail(PG_EINVAL, std::string(what) + " frame must be non-NULL");
+  if (f->n < 2 || f->n > 65536) return fail(PG_EINVAL, std::string(what) + " frame: n must be in [2, 65536]");
+  if (!(f->cell > 0.0) || !is_finite(f->cell)) return fail(PG_EINVAL, std::string(what) + " frame: cell must be positive and finite");
+  if (!is_finite(f->ra)) return fail(PG_EINVAL, std::string(what) + " frame: ra must be finite");
+  if (!(std::fabs(f->dec) <= 1.5707963267948966)) return fail(PG_EINVAL, std::string(what) + " frame: |dec| must be <= pi/2");
+  return PG_OK;
+}
+}  // namespace
+
+int pg_reproject(const float* src, const float* src_weight, const pg_sky_frame* src_frame, float* dst,
+                 float* dst_weight, const pg_sky_frame* dst_frame, int32_t npol, int32_t flags, void* stream) {
+  g_error.clear();
+  if (!src || !dst) return fail(PG_EINVAL, "src and dst must be non-NULL");
+  int rc = check_frame(src_frame, "source");
+  if (rc != PG_OK) return rc;
+  rc = check_frame(dst_frame, "destination");
+  if (rc != PG_OK) return rc;
+  if (npol < 1 || npol > 4) return fail(PG_EINVAL, "npol must be in [1, 4]");
+  if (flags & ~PG_ACCUMULATE) return fail(PG_EINVAL, "unknown flag bits");
+  PG_HIP(launch_reproject(src, src_weight, *src_frame, dst, dst_weight, *dst_frame, npol, (flags & PG_ACCUMULATE) != 0,
+                          static_cast<hipStream_t>(stream)),
+         "reproject");
+  return PG_OK;
+}
+
+int pg_weight_normalise(float* img, const float* weight, int32_t n, int32_t npol, float min_weight, void* stream) {
+  g_error.clear();
+  if (!img || !weight) return fail(PG_EINVAL, "img and weight must be non-NULL");
+  if (n < 1 || n > 65536) return fail(PG_EINVAL, "n must be in [1, 65536]");
+  if (npol < 1 || npol > 4) return fail(PG_EINVAL, "npol must be in [1, 4]");
+  if (!(min_weight > 0.0f) || !std::isfinite(min_weight)) return fail(PG_EINVAL, "min_weight must be positive and finite");
+  PG_HIP(launch_weight_normalise(img, weight, n, npol, min_weight, static_cast<hipStream_t>(stream)), "normalise");
   return PG_OK;
 }
 

@@ -1,0 +1,9 @@
+// Launchers of the image-domain mosaic kernels (mosaic.hip).
+#pragma once
+#include "common.hpp"
+
+namespace pg {
+hipError_t launch_reproject(const float* src, const float* src_w, const pg_sky_frame& sf, float* dst, float* dst_w,
+                            const pg_sky_frame& df, int npol, int accumulate, hipStream_t s);
+hipError_t launch_weight_normalise(float* img, const float* weight, int n, int npol, float min_weight, hipStream_t s);
+}  // namespace pg

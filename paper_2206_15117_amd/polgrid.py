@@ -49,6 +49,10 @@ class PgField(ctypes.Structure):
     _fields_ = [("plan", c_void_p), ("kernels", c_void_p), ("vis", c_void_p), ("grid", c_void_p)]
 
 
+class PgSkyFrame(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("cell", c_double), ("ra", c_double), ("dec", c_double)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
 
@@ -73,6 +77,9 @@ EXPORTS = {
     "pg_batch_degrid": (c_int, [c_void_p, c_int32, c_void_p]),
     "pg_batch_work_items": (c_int64, [c_void_p]),
     "pg_batch_destroy": (None, [c_void_p]),
+    "pg_reproject": (c_int, [c_void_p, c_void_p, POINTER(PgSkyFrame), c_void_p, c_void_p, POINTER(PgSkyFrame), c_int32,
+                             c_int32, c_void_p]),
+    "pg_weight_normalise": (c_int, [c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, c_void_p]),
     "pg_kernels_write_cell": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "pg_kernels_alloc": (c_int, [POINTER(PgKernelSpec), c_void_p, POINTER(c_void_p)]),
     "pg_hogbom": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, ctypes.c_float, c_int32,
@@ -372,6 +379,50 @@ def predict(p: Plan, k: Kernels, model, out=None, buf=None, subtract: bool = Fal
     taper(k, model, buf, TAPER_PREDICT, -1.0 if subtract else 1.0)
     g = torch.fft.ifft2(buf, norm="forward")
     return degrid(p, k, g, out=out, fftshift=True, accumulate=subtract)
+
+
+def _frame(f) -> PgSkyFrame:
+    """A sky frame (n, cell, ra, dec) (tuple, namedtuple or object with those attributes)."""
+    if hasattr(f, "cell"):
+        return PgSkyFrame(int(f.n), float(f.cell), float(f.ra), float(f.dec))
+    n, cell, ra, dec = f
+    return PgSkyFrame(int(n), float(cell), float(ra), float(dec))
+
+
+def _image_check(t, npol: int, n: int, what: str):
+    import torch
+
+    if t.dtype != torch.float32 or tuple(t.shape[-2:]) != (n, n) or not t.is_contiguous() or t.numel() != npol * n * n:
+        raise ValueError(f"{what} must be a contiguous float32 [{npol}][{n}][{n}] device tensor")
+
+
+def reproject(src, src_frame, dst, dst_frame, src_weight=None, dst_weight=None, accumulate: bool = False,
+              stream=None):
+    """Image-plane reprojection of src (float32 [npol][n][n], frame src_frame) onto dst (frame
+    dst_frame): without accumulate dst = the bilinear samples (dst_weight = the sampled weight);
+    with accumulate dst += weight x sample and dst_weight += weight."""
+    sf, df = _frame(src_frame), _frame(dst_frame)
+    npol = src.shape[0] if src.dim() == 3 else 1
+    _image_check(src, npol, sf.n, "src")
+    _image_check(dst, npol, df.n, "dst")
+    if src_weight is not None:
+        _image_check(src_weight, 1, sf.n, "src_weight")
+    if dst_weight is not None:
+        _image_check(dst_weight, 1, df.n, "dst_weight")
+    _check(lib().pg_reproject(_ptr(src), _ptr(src_weight) if src_weight is not None else None, ctypes.byref(sf),
+                              _ptr(dst), _ptr(dst_weight) if dst_weight is not None else None, ctypes.byref(df),
+                              npol, ACCUMULATE if accumulate else 0, _stream(stream)))
+    return dst
+
+
+def weight_normalise(img, weight, min_weight: float, stream=None):
+    """img /= weight where weight >= min_weight, else 0 (in place)."""
+    n = img.shape[-1]
+    npol = img.shape[0] if img.dim() == 3 else 1
+    _image_check(img, npol, n, "img")
+    _image_check(weight, 1, n, "weight")
+    _check(lib().pg_weight_normalise(_ptr(img), _ptr(weight), n, npol, float(min_weight), _stream(stream)))
+    return img
 
 
 def hogbom(residual, psf, mask=None, gain: float = 0.1, threshold: float = 0.0, max_iter: int = 1000,

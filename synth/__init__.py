@@ -427,3 +427,27 @@ def config5(seed: int = SEED_BASE + 5, nvis: int = 20_000_000, n: int = 8192, ce
     sl, sm, iquv = polarised_sources(nsrc, 1.0 * DEG, rng)
     return Workload(f"c5-majorcycle-{n}", geom, uvw, 4, sl, sm, iquv, beam, 0.2,
                     extra={"freq_hz": f0 + 0.5 * (nchan - 1) * df, "n_chan": nchan, "dumps_per_chan": per_chan})
+
+
+def mosaic7_pointings(ra0: float, dec0: float, spacing: float):
+    """Seven pointing centres (radians): ra0, dec0 and a hexagon of six at `spacing` radians."""
+    out = [(ra0, dec0)]
+    for k in range(6):
+        a = k * math.pi / 3.0
+        out.append((ra0 + spacing * math.cos(a) / math.cos(dec0), dec0 + spacing * math.sin(a)))
+    return out
+
+
+def config5_mosaic(nfields: int = 7, spacing: float = 0.5 * DEG, ra0: float = 1.0, dec0: float = -45.0 * DEG,
+                   pad: float = 1.25, **kw):
+    """The major-cycle workload as a 7-field image-domain mosaic: config 5's 20M rows split into
+    seven consecutive blocks (channel ranges), one per pointing (the centre and a hexagon at
+    half the 1-degree beam width), each field imaged on its own 8192^2 x 4 frame about its
+    pointing; the mosaic frame has the same cell, centred on the middle pointing, `pad` times
+    the field size.  Returns (workload, list of (ra, dec) field centres, mosaic frame (n, cell,
+    ra, dec))."""
+    w = config5(**kw)
+    centres = mosaic7_pointings(ra0, dec0, spacing)[:nfields]
+    nm = int(round(w.geom.n * pad / 16.0)) * 16
+    return w, centres, (nm, w.geom.cell, ra0, dec0)
+

@@ -108,6 +108,10 @@ def test_null_handles_are_rejected():
     assert lib.pg_plan_set_launch(None, 0, 16, 16, 1, 0) == pg.EINVAL
     assert lib.pg_kernels_alloc(None, None, ctypes.byref(h)) == pg.EINVAL
     assert lib.pg_kernels_export(None, 0, 1, None, None) == pg.EINVAL
+    f = pg.PgSkyFrame(64, 1e-4, 0.0, 0.0)
+    assert lib.pg_reproject(None, None, f, None, None, f, 4, 0, None) == pg.EINVAL
+    assert lib.pg_reproject(1024, None, None, 2048, None, f, 4, 0, None) == pg.EINVAL
+    assert lib.pg_weight_normalise(None, None, 64, 4, 1.0, None) == pg.EINVAL
     assert lib.pg_kernels_import(None, 0, 1, None, None, None) == pg.EINVAL
     lib.pg_kernels_destroy(None)
     lib.pg_plan_destroy(None)
