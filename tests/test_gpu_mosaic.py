@@ -163,3 +163,41 @@ def test_three_field_mosaic_through_the_imaging_path():
         assert rel(buf.cpu().numpy(), ref_model) < TOL
         direct = pg.predict(f.plan, kd, buf)
         assert rel(vpred.cpu().numpy(), direct.cpu().numpy()) < 1e-6
+
+
+def test_full_size_reprojection_sampled():
+    """The benchmark's shapes: a 8192^2 x 4 field at an outer pointing of the hexagon, accumulated
+    with its weight onto the 10240^2 x 4 mosaic frame, and the mosaic resampled back onto the
+    field; 4000 seeded destination pixels of each checked against the float64 reference evaluated
+    pixel by pixel."""
+    n, cell = 8192, 1.76 * math.pi / 180.0 / 3600.0
+    centres = synth.mosaic7_pointings(1.0, -45.0 * DEG, 0.5 * DEG)
+    field = mos.SkyFrame(n, cell, *centres[4])
+    mframe = mos.SkyFrame(10240, cell, 1.0, -45.0 * DEG)
+    rng = np.random.default_rng(55)
+    src = torch.randn((4, n, n), dtype=torch.float32, device="cuda")
+    wsrc = torch.rand((n, n), dtype=torch.float32, device="cuda")
+    out = torch.zeros((4, mframe.n, mframe.n), dtype=torch.float32, device="cuda")
+    ow = torch.zeros((mframe.n, mframe.n), dtype=torch.float32, device="cuda")
+    pg.reproject(src, field, out, mframe, src_weight=wsrc, dst_weight=ow, accumulate=True)
+    back = torch.empty((4, n, n), dtype=torch.float32, device="cuda")
+    pg.reproject(out, mframe, back, field)
+    src_h, w_h, out_h, ow_h, back_h = (t.cpu().numpy() for t in (src, wsrc, out, ow, back))
+
+    def ref(img, sfr, dfr, ii, jj, weight=None):
+        l0, m0 = (jj - dfr.n // 2) * dfr.cell, (ii - dfr.n // 2) * dfr.cell
+        ra, dec = omos.lm_to_radec(l0, m0, dfr.ra, dfr.dec)
+        l, m, nn = omos.radec_to_lm(ra, dec, sfr.ra, sfr.dec)
+        x, y = l / sfr.cell + sfr.n // 2, m / sfr.cell + sfr.n // 2
+        v, inside = omos.bilinear(img.astype(np.float64), x, y)
+        cov = inside & (nn > 0)
+        wv = np.where(cov, omos.bilinear(weight.astype(np.float64), x, y)[0], 0.0) if weight is not None else cov * 1.0
+        return np.where(cov, v, 0.0), wv
+
+    ii, jj = rng.integers(0, mframe.n, 4000), rng.integers(0, mframe.n, 4000)
+    v, wv = ref(src_h, field, mframe, ii, jj, w_h)
+    assert 0.3 < (wv > 0).mean() < 0.9
+    assert rel(out_h[:, ii, jj], wv * v) < TOL and rel(ow_h[ii, jj], wv) < TOL
+    ii, jj = rng.integers(0, n, 4000), rng.integers(0, n, 4000)
+    v, _ = ref(out_h, mframe, field, ii, jj)
+    assert rel(back_h[:, ii, jj], v) < TOL
