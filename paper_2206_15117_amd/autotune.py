@@ -25,7 +25,7 @@ Launch = namedtuple("Launch", "geom max_chunk variant grid_waves degrid_waves xc
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
 LDS_CU = 163840            # LDS per CU
-LDS_SCRATCH = 1280         # per-workgroup gridder scratch (row loads, band bounds, queue slot)
+LDS_SCRATCH = 1280         # per-workgroup gridder scratch (row loads and band bounds), rounded up
 
 
 def lds_pitch(width: int, support: int) -> int:
@@ -34,7 +34,9 @@ def lds_pitch(width: int, support: int) -> int:
 
 def tiles_for(support, npol: int, wgs_per_cu: int, min_tile: int = 1):
     """Largest tile per plane whose (T+S-1) x pitch x npol x 8 B sub-grid, plus the gridder
-    scratch, lets wgs_per_cu workgroups share one CU's LDS."""
+    scratch, lets wgs_per_cu workgroups share one CU's LDS.  All npol planes count: the degridder
+    holds every plane, and grid and degrid share one plan (a gridder with fewer output planes per
+    workgroup then fits more workgroups per CU)."""
     budget = LDS_CU // wgs_per_cu - LDS_SCRATCH
     out = []
     for s in np.asarray(support):
