@@ -176,10 +176,13 @@ void pg_plan_destroy(pg_plan* p);
  * its L2 (1 = plain order, up to 4096); grid_planes = output correlation planes per row-band
  * workgroup, 0 (all), 1, 2 or 4: with 1 or 2, npol / grid_planes workgroups share each work item,
  * each holding only its planes' sub-grid in LDS and reading only its rows of the 4x4 Mueller
- * kernels (ignored where it does not divide npol).  Set before the plan is shared between threads.
- * Errors: PG_EINVAL. */
+ * kernels (ignored where it does not divide npol); degrid_corrs = output correlations per degrid
+ * workgroup, 0 (all), 2 or 4: with 2 (float32 full-pol tables only, ignored otherwise) two
+ * workgroups share each work item, each reading the half of the Mueller kernels its two
+ * correlations need, placed on alternate XCDs (the XCD grouping is then not applied to the
+ * degrid).  Set before the plan is shared between threads.  Errors: PG_EINVAL. */
 int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves,
-                       int32_t xcd_group, int32_t grid_planes);
+                       int32_t xcd_group, int32_t grid_planes, int32_t degrid_corrs);
 
 /* Gridding (Sec. 3.2, Sec. 4):
  *   G_q(X,Y) (+)= sum_k sum_c T_{p_k,q,c}(X os - fine_x,k, Y os - fine_y,k) V_{k,c}.

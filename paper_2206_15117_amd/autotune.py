@@ -4,7 +4,8 @@ Searches, per geometry class (npol, storage, os, per-plane supports):
   * workgroups per CU (1-4): sets each plane's tile T to the largest sub-grid that fits
     1/k of the LDS, so every item of a launch has the same LDS footprint;
   * waves per workgroup for grid and degrid (4, 6, 8, 16);
-  * output planes per gridder workgroup (all, 2 or 1 of the four correlations);
+  * output planes per gridder workgroup (all, 2 or 1 of the four correlations), and output
+    correlations per degridder workgroup (all or 2, float32 tables);
   * the grid variant (row bands or LDS atomics) and the chunk length of work items;
   * how many consecutive work items share one XCD (and its L2), for the best shape found.
 Each candidate is timed with HIP events on a representative workload; the best choice is
@@ -20,7 +21,7 @@ from collections import namedtuple
 import numpy as np
 
 Launch = namedtuple("Launch", "geom max_chunk variant grid_waves degrid_waves xcd_group batch_grid_waves "
-                               "batch_degrid_waves grid_planes")
+                               "batch_degrid_waves grid_planes degrid_corrs")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
@@ -89,14 +90,14 @@ def apply(geom, npol, storage) -> Launch:
     cfg = tuned_config(npol, storage, geom.os, geom.support)
     g = copy.copy(geom)
     if cfg is None:
-        return Launch(g, 1024, 0, 16, 16, 1, 16, 16, 0)
+        return Launch(g, 1024, 0, 16, 16, 1, 16, 16, 0, 0)
     g.tile = np.asarray(cfg["grid"]["tiles"], dtype=np.int32)
     same = cfg["grid"]["wgs_per_cu"] == cfg["degrid"]["wgs_per_cu"]
     gw, dw = int(cfg["grid"]["waves"]), int(cfg["degrid"]["waves"]) if same else 16
     batch = cfg.get("batch", {})
     return Launch(g, int(cfg["grid"]["max_chunk"]), int(cfg["grid"].get("variant", 2)), gw, dw,
                   int(cfg.get("xcd_group", 1)), int(batch.get("grid_waves", gw)), int(batch.get("degrid_waves", dw)),
-                  int(cfg["grid"].get("planes", 0)))
+                  int(cfg["grid"].get("planes", 0)), int(cfg["degrid"].get("corrs", 0)))
 
 
 def batch_plans(kernels_grid, kernels_degrid, uvw, launch: Launch):
@@ -106,8 +107,10 @@ def batch_plans(kernels_grid, kernels_degrid, uvw, launch: Launch):
 
     pg_ = pg.plan(kernels_grid, uvw, max_chunk=launch.max_chunk)
     pd_ = pg.plan(kernels_degrid, uvw, max_chunk=launch.max_chunk)
-    pg_.set_launch(0, launch.batch_grid_waves, launch.degrid_waves, launch.xcd_group, launch.grid_planes)
-    pd_.set_launch(0, launch.grid_waves, launch.batch_degrid_waves, launch.xcd_group, launch.grid_planes)
+    pg_.set_launch(0, launch.batch_grid_waves, launch.degrid_waves, launch.xcd_group, launch.grid_planes,
+                   launch.degrid_corrs)
+    pd_.set_launch(0, launch.grid_waves, launch.batch_degrid_waves, launch.xcd_group, launch.grid_planes,
+                   launch.degrid_corrs)
     return pg_, pd_
 
 
@@ -116,7 +119,8 @@ def plan(kernels, uvw, launch: Launch):
     from . import polgrid as pg
 
     return pg.plan(kernels, uvw, max_chunk=launch.max_chunk).set_launch(0, launch.grid_waves, launch.degrid_waves,
-                                                                        launch.xcd_group, launch.grid_planes)
+                                                                        launch.xcd_group, launch.grid_planes,
+                                                                        launch.degrid_corrs)
 
 
 def _time(fn, reps):
@@ -161,7 +165,13 @@ def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2
                     p.set_launch(variant, nw, nw, 1, gp)
                     tg = _time(lambda: pg.grid(p, kg, vis, out=grid, fftshift=True), reps)
                     td = _time(lambda: pg.degrid(p, kd, grid, out=out, fftshift=True), reps)
-                    r = dict(wgs_per_cu=k, max_chunk=chunk, waves=nw, variant=variant, planes=gp,
+                    corrs = 0
+                    if storage == 0 and npol == 4 and gp == planes[0]:
+                        p.set_launch(variant, nw, nw, 1, gp, 2)
+                        td2 = _time(lambda: pg.degrid(p, kd, grid, out=out, fftshift=True), reps)
+                        if td2 < td:
+                            td, corrs = td2, 2
+                    r = dict(wgs_per_cu=k, max_chunk=chunk, waves=nw, variant=variant, planes=gp, corrs=corrs,
                              grid_ms=tg, degrid_ms=td, tiles=tiles.tolist())
                     results.append(r)
                     if verbose:
@@ -171,7 +181,7 @@ def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2
     best = dict(grid=dict(wgs_per_cu=bg["wgs_per_cu"], max_chunk=bg["max_chunk"], waves=bg["waves"],
                           variant=bg["variant"], planes=bg["planes"], ms=bg["grid_ms"], tiles=bg["tiles"]),
                 degrid=dict(wgs_per_cu=bd["wgs_per_cu"], max_chunk=bd["max_chunk"], waves=bd["waves"],
-                            ms=bd["degrid_ms"], tiles=bd["tiles"]))
+                            corrs=bd["corrs"], ms=bd["degrid_ms"], tiles=bd["tiles"]))
     # XCD grouping for the best grid shape: sum of grid and degrid time
     g = copy.copy(geom)
     g.tile = np.asarray(bg["tiles"], dtype=np.int32)
@@ -180,7 +190,7 @@ def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2
     p = pg.plan(kg, uvw, max_chunk=bg["max_chunk"])
     best_x = (float("inf"), 1)
     for xg in (1, 2, 4, 8, 16, 32):
-        p.set_launch(bg["variant"], bg["waves"], bd["waves"], xg, bg["planes"])
+        p.set_launch(bg["variant"], bg["waves"], bd["waves"], xg, bg["planes"], bd["corrs"])
         t = (_time(lambda: pg.grid(p, kg, vis, out=grid, fftshift=True), reps)
              + _time(lambda: pg.degrid(p, kd, grid, out=out, fftshift=True), reps))
         results.append(dict(xcd_group=xg, grid_plus_degrid_ms=t))

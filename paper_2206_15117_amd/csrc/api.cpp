@@ -353,7 +353,7 @@ int pg_plan_copy(const pg_plan* p, int32_t* perm, int32_t* fine, int32_t* items,
 void pg_plan_destroy(pg_plan* p) { delete p; }
 
 int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int32_t degrid_waves,
-                       int32_t xcd_group, int32_t grid_planes) {
+                       int32_t xcd_group, int32_t grid_planes, int32_t degrid_corrs) {
   g_error.clear();
   if (!p) return fail(PG_EINVAL, "plan must be non-NULL");
   if (grid_variant < 0 || grid_variant > 2) return fail(PG_EINVAL, "grid_variant must be 0, 1 or 2");
@@ -362,8 +362,11 @@ int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int
   if (xcd_group < 1 || xcd_group > 4096) return fail(PG_EINVAL, "xcd_group must be in [1, 4096]");
   if (grid_planes != 0 && grid_planes != 1 && grid_planes != 2 && grid_planes != 4)
     return fail(PG_EINVAL, "grid_planes must be 0, 1, 2 or 4");
+  if (degrid_corrs != 0 && degrid_corrs != 2 && degrid_corrs != 4)
+    return fail(PG_EINVAL, "degrid_corrs must be 0, 2 or 4");
   p->xcd_group = xcd_group;
   p->grid_planes = grid_planes;
+  p->degrid_corrs = degrid_corrs;
   p->grid_variant = grid_variant;
   p->grid_waves = grid_waves;
   p->degrid_waves = degrid_waves;

@@ -141,6 +141,7 @@ struct pg_plan {
   int32_t grid_waves = 16, degrid_waves = 16;  // waves per workgroup
   int32_t xcd_group = 1;                // consecutive work items kept on one XCD
   int32_t grid_planes = 0;              // output planes per banded-gridder workgroup (0: all)
+  int32_t degrid_corrs = 0;             // correlations per degrid workgroup (0: all; 2 for float32 full-pol)
   std::vector<int32_t> support, tile;
   pg::DevBuf perm;    // int32 [nvis]
   pg::DevBuf fine;    // int2 [n_kept]

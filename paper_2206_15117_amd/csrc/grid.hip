@@ -78,6 +78,13 @@ struct TapChunks {
 #pragma unroll
     for (int j = 0; j < NCH; ++j) base[j] = uniform_base(reinterpret_cast<const char*>(ph) + j * chunk_bytes);
   }
+  // chunks first, first + stride, ... of the phase block ph
+  __device__ TapChunks(const TapT* ph, int ss, int first, int stride) {
+    const uint32_t chunk_bytes = static_cast<uint32_t>(ss) * kTapBytes;
+#pragma unroll
+    for (int j = 0; j < NCH; ++j)
+      base[j] = uniform_base(reinterpret_cast<const char*>(ph) + static_cast<size_t>(first + j * stride) * chunk_bytes);
+  }
   // All npol^2 taps of tap index t: per chunk, one scalar base plus a 32-bit lane offset.
   __device__ void load(uint32_t t, float2 (&out)[NQC]) const { load_at(t * kTapBytes, out); }
   __device__ void load_at(uint32_t boff, float2 (&out)[NQC]) const {
@@ -501,28 +508,31 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_batch(const FieldArgs* __
 // tile), degridded together: every tap is loaded once and applied to all R rows, whose sub-grid
 // positions differ by a wave-uniform offset.  One 64-lane sum per row and output value; lane 63
 // writes the rows' visibilities.
-template <int NP, typename TapT, int R>
+template <int NP, typename TapT, int R, int NC = NP>
 __device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase_table, int j, int m_ly, int m_lx,
                                             int m_k, int S, int SS, int P, int WP, float inv_s,
                                             const FootStep& step, float2* __restrict__ vis_out, int flags,
-                                            int lane) {
-  const TapChunks<NP * NP, TapT> tc(phase_table, SS);
+                                            int lane, int c0 = 0) {
+  // NC < NP: this workgroup computes correlations c0 .. c0 + NC - 1, from Mueller entries (q, c0 ..)
+  // which sit in every (NP / NC)-th 16-byte chunk of the phase block
+  const TapChunks<NP * NC, TapT> tc = NC == NP ? TapChunks<NP * NC, TapT>(phase_table, SS)
+                                               : TapChunks<NP * NC, TapT>(phase_table, SS, c0 / NC, NP / NC);
   const int ly0 = __builtin_amdgcn_readlane(m_ly, j), lx0 = __builtin_amdgcn_readlane(m_lx, j);
   int d[R];
 #pragma unroll
   for (int r = 0; r < R; ++r)
     d[r] = (__builtin_amdgcn_readlane(m_ly, j + r) - ly0) * P + (__builtin_amdgcn_readlane(m_lx, j + r) - lx0);
-  float acc[R][2 * NP];
+  float acc[R][2 * NC];
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int c = 0; c < 2 * NP; ++c) acc[r][c] = 0.0f;
-  constexpr uint32_t TB = TapChunks<NP * NP, TapT>::kTapBytes;
+    for (int c = 0; c < 2 * NC; ++c) acc[r][c] = 0.0f;
+  constexpr uint32_t TB = TapChunks<NP * NC, TapT>::kTapBytes;
   TapCursor cur(lane, ly0, lx0, inv_s, S, P);
   uint32_t boff = static_cast<uint32_t>(lane) * TB;
 #pragma unroll(R == 1 ? 2 : 1)
   for (int t = lane; t < SS; t += 64) {
-    float2 tap[NP * NP];
+    float2 tap[NP * NC];
     tc.load_at(boff, tap);
     const int off = cur.off;
     boff += 64 * TB;
@@ -533,8 +543,8 @@ __device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase
       for (int q = 0; q < NP; ++q) {
         const float2 g = lds[q * WP + off + d[r]];
 #pragma unroll
-        for (int c = 0; c < NP; ++c) {
-          const float2 a = tap[q * NP + c];  // conj(a) * g
+        for (int c = 0; c < NC; ++c) {
+          const float2 a = tap[q * NC + c];  // conj(a) * g
           acc[r][2 * c] = fmaf(a.x, g.x, fmaf(a.y, g.y, acc[r][2 * c]));
           acc[r][2 * c + 1] = fmaf(a.x, g.y, fmaf(-a.y, g.x, acc[r][2 * c + 1]));
         }
@@ -544,27 +554,27 @@ __device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase
 #pragma unroll
   for (int r = 0; r < R; ++r) {
 #pragma unroll
-    for (int c = 0; c < 2 * NP; ++c) acc[r][c] = wave_sum_to_lane63(acc[r][c]);
+    for (int c = 0; c < 2 * NC; ++c) acc[r][c] = wave_sum_to_lane63(acc[r][c]);
     const int k = __builtin_amdgcn_readlane(m_k, j + r);
     if (lane == 63) {
 #pragma unroll
-      for (int c = 0; c < NP; ++c)
+      for (int c = 0; c < NC; ++c)
         if (flags & PG_ACCUMULATE) {
-          float2& o = vis_out[static_cast<size_t>(k) * NP + c];
+          float2& o = vis_out[static_cast<size_t>(k) * NP + c0 + c];
           o = make_float2(o.x + acc[r][2 * c], o.y + acc[r][2 * c + 1]);
         } else {
-          vis_out[static_cast<size_t>(k) * NP + c] = make_float2(acc[r][2 * c], acc[r][2 * c + 1]);
+          vis_out[static_cast<size_t>(k) * NP + c0 + c] = make_float2(acc[r][2 * c], acc[r][2 * c + 1]);
         }
     }
   }
 }
 
-template <int NP, typename TapT, int NW>
+template <int NP, typename TapT, int NW, int NC = NP>
 __device__ __forceinline__ void degrid_item(const Item it, const int2* __restrict__ fine,
                                             const int32_t* __restrict__ perm, const TapT* __restrict__ table,
                                             const PlaneInfo* __restrict__ planes, int os, int n,
                                             const float2* __restrict__ grid, float2* __restrict__ vis_out,
-                                            int flags, float* lds_f) {
+                                            int flags, float* lds_f, int c0 = 0) {
   float2* lds = reinterpret_cast<float2*>(lds_f);  // [q][W][P]
   const PlaneInfo pl = planes[it.plane];
   const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
@@ -608,19 +618,22 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
       run = __builtin_amdgcn_readfirstlane(run);
       const TapT* pt = table + pl.offset + static_cast<size_t>(ph) * SS * NP * NP;
       if (run == 4) {
-        degrid_rows<NP, TapT, 4>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane);
+        degrid_rows<NP, TapT, 4, NC>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane,
+                                    c0);
       } else if (run >= 2) {
-        degrid_rows<NP, TapT, 2>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane);
+        degrid_rows<NP, TapT, 2, NC>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane,
+                                    c0);
         run = 2;
       } else {
-        degrid_rows<NP, TapT, 1>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane);
+        degrid_rows<NP, TapT, 1, NC>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane,
+                                    c0);
       }
       j += run;
     }
   }
 }
 
-template <int NP, typename TapT, int NW>
+template <int NP, typename TapT, int NW, int NC = NP>
 __global__ __launch_bounds__(NW * 64) void degrid_kernel(const Item* __restrict__ items,
                                                          const int2* __restrict__ fine,
                                                          const int32_t* __restrict__ perm,
@@ -630,9 +643,12 @@ __global__ __launch_bounds__(NW * 64) void degrid_kernel(const Item* __restrict_
                                                          float2* __restrict__ vis_out, int flags, int n_items,
                                                          int group) {
   extern __shared__ float lds_f[];
-  const int item = xcd_item(blockIdx.x, group);
+  // NP / NC workgroups per item, each computing NC of the correlations
+  const int w = xcd_item(blockIdx.x, group);
+  const int item = w / (NP / NC), part = w - item * (NP / NC);
   if (item >= n_items) return;
-  degrid_item<NP, TapT, NW>(items[item], fine, perm, table, planes, os, n, grid, vis_out, flags, lds_f);
+  degrid_item<NP, TapT, NW, NC>(items[item], fine, perm, table, planes, os, n, grid, vis_out, flags, lds_f,
+                                part * NC);
 }
 
 template <int NP, typename TapT, int NW>
@@ -745,6 +761,22 @@ hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, fl
 template <int NP, typename TapT, int NW>
 hipError_t run_degrid_nw(const pg_plan* p, const pg_kernels* k, const float2* grid, float2* vis, int flags,
                          hipStream_t s) {
+  // Two workgroups per item, each computing two of the four correlations from every second
+  // 16-byte chunk of the float32 table (Mueller entries (q, c) with c in its pair).  Blocks 2i and
+  // 2i + 1 take item i, so with the hardware's round-robin over the 8 XCDs every even XCD holds
+  // the first half of the tables in its L2 and every odd XCD the second (the plan's XCD grouping
+  // is not applied here).
+  if constexpr (NP == 4 && sizeof(TapT) == 8) {
+    if (p->degrid_corrs == 2) {
+      auto fn = degrid_kernel<NP, TapT, NW, 2>;
+      hipError_t e = allow_lds(fn, k->lds_bytes);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items * 2)), dim3(NW * 64), k->lds_bytes, s,
+                         p->items.as<Item>(), p->fine.as<int2>(), p->perm.as<int32_t>(), k->table.as<TapT>(),
+                         k->planes.as<PlaneInfo>(), k->os, k->n, grid, vis, flags, static_cast<int>(p->n_items), 1);
+      return hipGetLastError();
+    }
+  }
   auto fn = degrid_kernel<NP, TapT, NW>;
   hipError_t e = allow_lds(fn, k->lds_bytes);
   if (e != hipSuccess) return e;

@@ -68,7 +68,7 @@ EXPORTS = {
     "pg_plan_info": (c_int, [c_void_p, POINTER(PgPlanDesc)]),
     "pg_plan_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pg_plan_destroy": (None, [c_void_p]),
-    "pg_plan_set_launch": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32]),
+    "pg_plan_set_launch": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "pg_grid": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "pg_degrid": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "pg_taper": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_double, c_void_p]),
@@ -293,11 +293,12 @@ class Plan:
         return perm[:self.nvis], fine[:self.n_kept], items[:self.n_items]
 
     def set_launch(self, grid_variant: int = 0, grid_waves: int = 16, degrid_waves: int = 16, xcd_group: int = 1,
-                   grid_planes: int = 0):
+                   grid_planes: int = 0, degrid_corrs: int = 0):
         """Launch tuning (grid variant 0 auto / 1 atomic / 2 banded, waves per workgroup, consecutive
-        work items per XCD, output planes per banded-gridder workgroup: 0 = all, 1, 2 or 4)."""
+        work items per XCD, output planes per banded-gridder workgroup: 0 = all, 1, 2 or 4, output
+        correlations per degrid workgroup: 0 = all, 2 or 4)."""
         _check(lib().pg_plan_set_launch(self._h, int(grid_variant), int(grid_waves), int(degrid_waves),
-                                        int(xcd_group), int(grid_planes)))
+                                        int(xcd_group), int(grid_planes), int(degrid_corrs)))
         return self
 
     def __del__(self):

@@ -105,7 +105,7 @@ def test_null_handles_are_rejected():
     assert lib.pg_plan_info(None, None) == pg.EINVAL
     assert lib.pg_plan_copy(None, None, None, None, None) == pg.EINVAL
     assert lib.pg_kernels_copy_table(None, None, None) == pg.EINVAL
-    assert lib.pg_plan_set_launch(None, 0, 16, 16, 1, 0) == pg.EINVAL
+    assert lib.pg_plan_set_launch(None, 0, 16, 16, 1, 0, 0) == pg.EINVAL
     assert lib.pg_kernels_alloc(None, None, ctypes.byref(h)) == pg.EINVAL
     assert lib.pg_kernels_export(None, 0, 1, None, None) == pg.EINVAL
     f = pg.PgSkyFrame(64, 1e-4, 0.0, 0.0)

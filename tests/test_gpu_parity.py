@@ -238,6 +238,24 @@ def test_c2_grid_output_plane_split(c2_case, planes, waves, group):
         assert rel(got, gridding.grid(w.geom, kernels.round_tables(tg, np.float16), w.uvw, vis)) < TOL
 
 
+@pytest.mark.parametrize("waves,storage", [(8, 0), (4, 0), (16, 0), (8, 1)])
+def test_c2_degrid_correlation_split(c2_case, waves, storage):
+    """Two workgroups per work item, each computing two of the four correlations from its half of
+    the float32 Mueller kernels, give the oracle visibilities; float16 tables ignore the setting."""
+    w, _, _, td, _, kd = c2_case
+    rng = np.random.default_rng(70 + waves)
+    g = (rng.standard_normal((4, 256, 256)) + 1j * rng.standard_normal((4, 256, 256))).astype(np.complex64)
+    k = kd if storage == 0 else gpu_kernels(w, pg.KIND_DEGRID, storage=pg.STORE_F16)
+    t = td if storage == 0 else kernels.round_tables(td, np.float16)
+    p = pg.plan(k, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves, 1, 0, 2)
+    got = host(pg.degrid(p, k, dev(g)))
+    want = gridding.degrid(w.geom, t, w.uvw, g)
+    for c in range(4):
+        assert rel(got[:, c], want[:, c]) < TOL, c
+    base = host(pg.degrid(pg.plan(k, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves), k, dev(g)))
+    assert np.array_equal(got, base)  # same arithmetic per correlation
+
+
 def test_c2_degrid_parity(c2_case):
     w, _, _, td, _, kd = c2_case
     rng = np.random.default_rng(4)
