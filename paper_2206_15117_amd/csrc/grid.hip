@@ -19,7 +19,8 @@
 //           sub-grid with LDS float atomics (narrow sub-grids only).
 //   degrid: the sub-grid is loaded once into LDS; each wave takes a run of the
 //           item's visibilities, degrids same-phase neighbours together and
-//           reduces each visibility's taps across the wave.
+//           reduces each visibility's taps across the wave; with float32 tables
+//           two workgroups can share an item, one per pair of correlations.
 #include "common.hpp"
 
 namespace pg {
