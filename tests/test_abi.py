@@ -144,3 +144,33 @@ def test_torch_allocator_hooks_are_created_once():
     pg.use_torch_allocator(True)
     assert pg._torch_hooks is first and first is not None
     pg.use_torch_allocator(False)
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/polgrid.h compiles as C99, and a C program links against the library and gets
+    argument errors back through the ABI without touching a GPU."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    inc = os.path.join(root, "include")
+    libdir = os.path.join(root, "paper_2206_15117_amd")
+    src = tmp_path / "abi.c"
+    src.write_text(
+        "#include <stdio.h>\n#include \"polgrid.h\"\n"
+        "int main(void) {\n"
+        "  pg_sky_frame f = {64, 1e-4, 0.0, 0.0};\n"
+        "  if (pg_reproject(NULL, NULL, &f, NULL, NULL, &f, 4, 0, NULL) != PG_EINVAL) return 1;\n"
+        "  if (pg_weight_normalise(NULL, NULL, 64, 4, 1.0f, NULL) != PG_EINVAL) return 2;\n"
+        "  if (pg_grid(NULL, NULL, NULL, NULL, 0, NULL) != PG_EINVAL) return 3;\n"
+        "  printf(\"%s\\n\", pg_last_error());\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "abi"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe), "-L", libdir,
+                    "-lpolgrid", "-Wl,-rpath," + libdir], check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert "non-NULL" in r.stdout
