@@ -5,7 +5,11 @@ its own pointing centre; image-plane reprojection then builds the mosaic at one 
 centre; before the degridding stage of clean the model image is reprojected back to the phase
 centre of each field, and each field gets its own FFT and degridding.
 
-The paper gives no formulas for this step; these are the readings used here:
+Phase rotation (listed with reprojection among the GPU-suited steps, Sec. 4) brings
+visibilities stored about one phase centre to another, so that a field can be imaged about its
+own pointing centre.
+
+The paper gives no formulas for these steps; these are the readings used here:
 - An image is an orthographic (SIN) projection about its phase centre (a0, d0).  Pixel (row i,
   column j) of an n x n image with cell size `cell` holds the direction cosines
   l = (j - n/2) cell, m = (i - n/2) cell (the gridder's image convention), with
@@ -21,6 +25,10 @@ The paper gives no formulas for this step; these are the readings used here:
 - The mosaic is the weighted mean  I = sum_f w_f I_f / sum_f w_f,  with w_f a weight image per
   field (for example the squared power beam inside the beam mask) reprojected like the image;
   mosaic pixels whose total weight is below `min_weight` are 0.
+- Phase rotation from centre A to centre B: the baseline b = u e_A + v n_A + w c_A (wavelengths,
+  on A's east/north/centre axes) gets coordinates (b.e_B, b.n_B, b.c_B) about B, and with the
+  predict convention V = sum I exp(+2 pi i (u l + v m + w (n - 1))) every correlation is
+  multiplied by exp(2 pi i (w_A - w_B)).
 Everything is float64.
 """
 import numpy as np
@@ -101,3 +109,20 @@ def mosaic(images, frames, weights, dst_frame, min_weight):
         num = num + w * v
         den = den + w
     return np.where(den >= min_weight, num / np.where(den > 0, den, 1.0), 0.0), den
+
+
+def axes(ra0, dec0):
+    """East, north and centre unit vectors of the frame about (ra0, dec0), rows of a 3 x 3 array."""
+    sa, ca, sd, cd = np.sin(ra0), np.cos(ra0), np.sin(dec0), np.cos(dec0)
+    return np.array([[-sa, ca, 0.0], [-sd * ca, -sd * sa, cd], [cd * ca, cd * sa, sd]])
+
+
+def phase_rotate(uvw, vis, centre_from, centre_to):
+    """(uvw about centre_to, vis about centre_to) from uvw float64 [nvis][3] and vis [nvis][npol]
+    about centre_from; centres are (ra, dec) in radians."""
+    uvw = np.asarray(uvw, dtype=np.float64)
+    b = uvw @ axes(*centre_from)           # baseline vectors, equatorial Cartesian
+    out = b @ axes(*centre_to).T
+    ph = np.exp(2j * np.pi * (uvw[:, 2] - out[:, 2]))
+    return out, np.asarray(vis, dtype=np.complex128) * ph[:, None]
+

@@ -9,12 +9,15 @@
   position directly.
 - Mosaic weighting: one field gives the field image where covered; fields that see the same
   constant sky give that constant on their union; low total weight gives 0.
+- Phase rotation: point-source visibilities predicted about one centre and rotated to another
+  equal the direct Fourier transform about the other centre; rotating onto the same centre
+  changes nothing; a round trip returns the input.
 """
 import math
 
 import numpy as np
 
-from oracle import mosaic
+from oracle import imaging, mosaic
 
 DEG = math.pi / 180.0
 
@@ -108,3 +111,27 @@ def test_mosaic_weighting():
     np.testing.assert_allclose(both[:, covered], 2.5, atol=1e-12)
     none, _ = mosaic.mosaic([const], [f1], [wa], dst, 10.0)
     assert np.all(none == 0)
+
+
+def test_phase_rotation_matches_the_direct_transform_about_the_new_centre():
+    rng = np.random.default_rng(7)
+    a = (1.2, -0.6)
+    b = (1.2 + 0.8 * DEG / math.cos(-0.6), -0.6 + 0.5 * DEG)
+    ra = a[0] + rng.uniform(-1, 1, 6) * DEG
+    dec = a[1] + rng.uniform(-1, 1, 6) * DEG
+    flux = rng.uniform(0.2, 1.0, (6, 1))
+    uvw = rng.uniform(-3000, 3000, (500, 3))
+    la, ma, _ = mosaic.radec_to_lm(ra, dec, *a)
+    va = imaging.dft_predict(uvw, la, ma, flux)
+    uvw_b, vb = mosaic.phase_rotate(uvw, va, a, b)
+    lb, mb, _ = mosaic.radec_to_lm(ra, dec, *b)
+    want = imaging.dft_predict(uvw_b, lb, mb, flux)
+    np.testing.assert_allclose(vb, want, rtol=0, atol=1e-9 * np.abs(want).max())
+    np.testing.assert_allclose(np.linalg.norm(uvw_b, axis=1), np.linalg.norm(uvw, axis=1), rtol=1e-13)
+    same_uvw, same = mosaic.phase_rotate(uvw, va, a, a)
+    np.testing.assert_allclose(same_uvw, uvw, atol=1e-9)
+    np.testing.assert_allclose(same, va, atol=1e-12)
+    back_uvw, back = mosaic.phase_rotate(uvw_b, vb, b, a)
+    np.testing.assert_allclose(back_uvw, uvw, atol=1e-8)
+    np.testing.assert_allclose(back, va, atol=1e-9)
+
