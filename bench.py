@@ -437,11 +437,12 @@ def bench_scale(steps, warmup):
 
 def bench_mosaic(steps, warmup):
     """The major cycle as a 7-field image-domain mosaic (Sec. 2.2): config 5's 20M rows in seven
-    fields, each imaged on its own 8192^2 x 4 frame about its pointing (plan -> grid -> FFT ->
-    taper) and reprojected, weighted by its squared power beam inside the eps = 0.2 mask, onto a
-    10240^2 mosaic frame; normalisation; then the mosaic reprojected back onto every field and
-    predicted (taper -> inverse FFT -> degrid).  Input visibilities: a 1000-component model
-    placed on the mosaic frame and predicted through the same path."""
+    fields, stored about the mosaic centre; each field's rows phase-rotated to its pointing and
+    imaged on its own 8192^2 x 4 frame (plan -> grid -> FFT -> taper), reprojected, weighted by
+    its squared power beam inside the eps = 0.2 mask, onto a 10240^2 mosaic frame;
+    normalisation; then the mosaic reprojected back onto every field and predicted (taper ->
+    inverse FFT -> degrid).  Input visibilities: a 1000-component model placed on the mosaic
+    frame and predicted through the same path."""
     import torch
 
     import synth
@@ -468,6 +469,7 @@ def bench_mosaic(steps, warmup):
     del x, pb
     plans = [autotune.plan(kg, u, launch) for u in uvws]
     fields = [mos.Field(fr, p, kg, kd, wimg, float(p.n_kept)) for fr, p in zip(frames, plans)]
+    mcentre = (mframe.ra, mframe.dec)
     model = torch.zeros((4, mframe.n, mframe.n), dtype=torch.float32, device="cuda")
     jj = np.clip(np.round(w.src_l / g.cell).astype(int) + mframe.n // 2, 0, mframe.n - 1)
     ii = np.clip(np.round(w.src_m / g.cell).astype(int) + mframe.n // 2, 0, mframe.n - 1)
@@ -476,14 +478,20 @@ def bench_mosaic(steps, warmup):
         model[q].view(-1).index_add_(0, idx, torch.from_numpy(w.src_iquv[:, q].astype(np.float32)).cuda())
     vis = mos.predict(fields, model, mframe)
     del model
+    # the visibilities as one measurement set holds them: all fields about the mosaic centre
+    stored = [pg.phase_rotate(u, v, (fr.ra, fr.dec), mcentre) for u, v, fr in zip(uvws, vis, frames)]
+    del vis, uvws
     log("mosaic inputs predicted")
+    uvw_w = torch.empty((max(int(u.shape[0]) for u, _ in stored), 3), dtype=torch.float64, device="cuda")
+    vis_w = torch.empty((uvw_w.shape[0], 4), dtype=torch.complex64, device="cuda")
     grid_buf = torch.empty((4, n, n), dtype=torch.complex64, device="cuda")
     pbuf = torch.empty_like(grid_buf)
     img = torch.empty((4, n, n), dtype=torch.float32, device="cuda")
     mimg = torch.empty((4, mframe.n, mframe.n), dtype=torch.float32, device="cuda")
     mw = torch.empty((mframe.n, mframe.n), dtype=torch.float32, device="cuda")
-    vis_out = [torch.empty_like(v) for v in vis]
-    stages = ("plan", "grid", "fft_taper", "reproject_to_mosaic", "normalise", "reproject_to_field", "predict")
+    vis_out = [torch.empty_like(v) for _, v in stored]
+    stages = ("phase_rotate", "plan", "grid", "fft_taper", "reproject_to_mosaic", "normalise", "reproject_to_field",
+              "predict")
     ev = {k: [] for k in stages}
 
     def mark(rec, k, a, b):
@@ -499,17 +507,23 @@ def bench_mosaic(steps, warmup):
         mimg.zero_()
         mw.zero_()
         for f in range(nf):
+            nv = stored[f][0].shape[0]
+            uw, vw = uvw_w[:nv], vis_w[:nv]
+            e_ = ev_now()
+            pg.phase_rotate(stored[f][0], stored[f][1], mcentre, (frames[f].ra, frames[f].dec), uvw_out=uw,
+                            vis_out=vw)
             e0 = ev_now()
-            p = autotune.plan(kg, uvws[f], launch)
+            p = autotune.plan(kg, uw, launch)
             e1 = ev_now()
-            pg.grid(p, kg, vis[f], out=grid_buf, fftshift=True)
+            pg.grid(p, kg, vw, out=grid_buf, fftshift=True)
             e2 = ev_now()
             pg.taper(kg, torch.fft.fft2(grid_buf), img, pg.TAPER_IMAGE, float(p.n_kept))
             e3 = ev_now()
             pg.reproject(img, frames[f], mimg, mframe, src_weight=wimg, dst_weight=mw, accumulate=True)
             e4 = ev_now()
             fields[f].plan = p
-            for k, a, b in (("plan", e0, e1), ("grid", e1, e2), ("fft_taper", e2, e3), ("reproject_to_mosaic", e3, e4)):
+            for k, a, b in (("phase_rotate", e_, e0), ("plan", e0, e1), ("grid", e1, e2), ("fft_taper", e2, e3),
+                            ("reproject_to_mosaic", e3, e4)):
                 mark(rec, k, a, b)
         e0 = ev_now()
         pg.weight_normalise(mimg, mw, 1e-3)
@@ -540,13 +554,17 @@ def bench_mosaic(steps, warmup):
     b_fld = nf * n * n * 4 * 8
     rep_gbs = (b_mos + b_fld) / ((ms["reproject_to_mosaic"] + ms["reproject_to_field"]) * 1e-3) / 1e9
     return {"workload": f"7-field image-domain mosaic of the major cycle: {nf} fields x {n}x{n}x4 (own phase centres, "
-                        f"hexagon at 0.5 deg), mosaic frame {mframe.n}x{mframe.n}x4, {w.nvis} rows in total, "
-                        f"{g.nplanes} w-planes",
+                        f"hexagon at 0.5 deg; rows stored about the mosaic centre and phase-rotated per field), "
+                        f"mosaic frame {mframe.n}x{mframe.n}x4, {w.nvis} rows in total, {g.nplanes} w-planes",
             "rows": w.nvis, "fields": nf, "value": w.nvis / wall, "unit": "vis/s", "ms_per_step": 1e3 * wall,
             "breakdown_ms": ms,
             "reproject_roofline": {"bound": "hbm", "achieved": rep_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                    "frac": rep_gbs / HBM_PEAK_GBS,
-                                   "bytes_per_step": b_mos + b_fld}}
+                                   "bytes_per_step": b_mos + b_fld},
+            # phase rotation: uvw (24 B) and 4 correlations (32 B) read and written per row
+            "phase_rotate_roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                                      "achieved": w.nvis * 112 / (ms["phase_rotate"] * 1e-3) / 1e9,
+                                      "frac": w.nvis * 112 / (ms["phase_rotate"] * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
 
 def bench_surrogate(n_kernels):

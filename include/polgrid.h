@@ -346,6 +346,18 @@ typedef struct pg_sky_frame {
 int pg_reproject(const float* src, const float* src_weight, const pg_sky_frame* src_frame, float* dst,
                  float* dst_weight, const pg_sky_frame* dst_frame, int32_t npol, int32_t flags, void* stream);
 
+/* Phase rotation (Sec. 4 lists it with reprojection among the GPU-suited steps): visibilities
+ * stored about phase centre (ra_from, dec_from) are moved to (ra_to, dec_to) (radians), so that a
+ * field can be imaged about its own pointing centre (Sec. 2.2).  Per row, with b = u e + v n + w c
+ * on the old centre's east/north/centre axes: uvw_out = (b.e', b.n', b.c') on the new centre's
+ * axes (float64), and every correlation is multiplied by exp(2 pi i (w - w')) (float64 phase,
+ * float32 complex product; the predict convention V = sum I exp(+2 pi i (u l + v m + w (n-1)))).
+ * uvw_in float64 [nvis][3], vis_in complex64 [nvis][npol], device memory; uvw_out (may be NULL)
+ * and vis_out likewise, the caller's; in place (out == in) is allowed.  npol 1..4.  Enqueue only.
+ * Errors: PG_EINVAL. */
+int pg_phase_rotate(const double* uvw_in, const void* vis_in, int64_t nvis, int32_t npol, double ra_from,
+                    double dec_from, double ra_to, double dec_to, double* uvw_out, void* vis_out, void* stream);
+
 /* Mosaic normalisation: img[q][p] = img[q][p] / weight[p] where weight[p] >= min_weight, else 0
  * (the weighted mean of the fields accumulated by pg_reproject).  img float32 [npol][n][n],
  * weight float32 [n][n], device memory.  min_weight > 0.  Enqueue only.  Errors: PG_EINVAL. */

@@ -552,6 +552,22 @@ int pg_reproject(const float* src, const float* src_weight, const pg_sky_frame* 
   return PG_OK;
 }
 
+int pg_phase_rotate(const double* uvw_in, const void* vis_in, int64_t nvis, int32_t npol, double ra_from,
+                    double dec_from, double ra_to, double dec_to, double* uvw_out, void* vis_out, void* stream) {
+  g_error.clear();
+  if (nvis < 0 || nvis > (int64_t(1) << 40)) return fail(PG_EINVAL, "nvis must be in [0, 2^40]");
+  if (nvis > 0 && (!uvw_in || !vis_in || !vis_out)) return fail(PG_EINVAL, "uvw_in, vis_in and vis_out must be non-NULL");
+  if (npol < 1 || npol > 4) return fail(PG_EINVAL, "npol must be in [1, 4]");
+  if (!is_finite(ra_from) || !is_finite(ra_to)) return fail(PG_EINVAL, "ra must be finite");
+  if (!(std::fabs(dec_from) <= 1.5707963267948966) || !(std::fabs(dec_to) <= 1.5707963267948966))
+    return fail(PG_EINVAL, "|dec| must be <= pi/2");
+  if (nvis == 0) return PG_OK;
+  PG_HIP(launch_phase_rotate(uvw_in, vis_in, nvis, npol, ra_from, dec_from, ra_to, dec_to, uvw_out, vis_out,
+                             static_cast<hipStream_t>(stream)),
+         "phase rotate");
+  return PG_OK;
+}
+
 int pg_weight_normalise(float* img, const float* weight, int32_t n, int32_t npol, float min_weight, void* stream) {
   g_error.clear();
   if (!img || !weight) return fail(PG_EINVAL, "img and weight must be non-NULL");

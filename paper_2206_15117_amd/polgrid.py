@@ -80,6 +80,8 @@ EXPORTS = {
     "pg_reproject": (c_int, [c_void_p, c_void_p, POINTER(PgSkyFrame), c_void_p, c_void_p, POINTER(PgSkyFrame), c_int32,
                              c_int32, c_void_p]),
     "pg_weight_normalise": (c_int, [c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, c_void_p]),
+    "pg_phase_rotate": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_double, c_double, c_double, c_double,
+                                c_void_p, c_void_p, c_void_p]),
     "pg_kernels_write_cell": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "pg_kernels_alloc": (c_int, [POINTER(PgKernelSpec), c_void_p, POINTER(c_void_p)]),
     "pg_hogbom": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, ctypes.c_float, c_int32,
@@ -414,6 +416,26 @@ def reproject(src, src_frame, dst, dst_frame, src_weight=None, dst_weight=None, 
                               _ptr(dst), _ptr(dst_weight) if dst_weight is not None else None, ctypes.byref(df),
                               npol, ACCUMULATE if accumulate else 0, _stream(stream)))
     return dst
+
+
+def phase_rotate(uvw, vis, centre_from, centre_to, uvw_out=None, vis_out=None, stream=None):
+    """Visibilities (complex64 [nvis][npol]) and uvw (float64 [nvis][3]) about centre_from moved to
+    centre_to ((ra, dec) radians).  Returns (uvw_out, vis_out); pass the inputs as outputs to
+    rotate in place."""
+    import torch
+
+    if uvw.dtype != torch.float64 or uvw.dim() != 2 or uvw.shape[1] != 3 or not uvw.is_contiguous():
+        raise ValueError("uvw must be a contiguous float64 [nvis, 3] device tensor")
+    if vis.dtype != torch.complex64 or vis.dim() != 2 or vis.shape[0] != uvw.shape[0] or not vis.is_contiguous():
+        raise ValueError("vis must be a contiguous complex64 [nvis, npol] device tensor")
+    if uvw_out is None:
+        uvw_out = torch.empty_like(uvw)
+    if vis_out is None:
+        vis_out = torch.empty_like(vis)
+    _check(lib().pg_phase_rotate(_ptr(uvw), _ptr(vis), uvw.shape[0], vis.shape[1], float(centre_from[0]),
+                                 float(centre_from[1]), float(centre_to[0]), float(centre_to[1]), _ptr(uvw_out),
+                                 _ptr(vis_out), _stream(stream)))
+    return uvw_out, vis_out
 
 
 def weight_normalise(img, weight, min_weight: float, stream=None):

@@ -112,6 +112,8 @@ def test_null_handles_are_rejected():
     assert lib.pg_reproject(None, None, f, None, None, f, 4, 0, None) == pg.EINVAL
     assert lib.pg_reproject(1024, None, None, 2048, None, f, 4, 0, None) == pg.EINVAL
     assert lib.pg_weight_normalise(None, None, 64, 4, 1.0, None) == pg.EINVAL
+    assert lib.pg_phase_rotate(None, None, 10, 4, 0.0, 0.0, 0.1, 0.1, None, None, None) == pg.EINVAL
+    assert lib.pg_phase_rotate(None, None, 0, 4, 0.0, 0.0, 0.1, 2.0, None, None, None) == pg.EINVAL
     assert lib.pg_kernels_import(None, 0, 1, None, None, None) == pg.EINVAL
     lib.pg_kernels_destroy(None)
     lib.pg_plan_destroy(None)
