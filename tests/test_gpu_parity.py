@@ -254,6 +254,11 @@ def test_c2_degrid_correlation_split(c2_case, waves, storage):
         assert rel(got[:, c], want[:, c]) < TOL, c
     base = host(pg.degrid(pg.plan(k, dev(w.uvw), max_chunk=100).set_launch(2, waves, waves), k, dev(g)))
     assert np.array_equal(got, base)  # same arithmetic per correlation
+    # accumulating onto existing visibilities (the subtracting prediction of clean)
+    start = (rng.standard_normal((w.nvis, 4)) + 1j * rng.standard_normal((w.nvis, 4))).astype(np.complex64)
+    acc = torch.from_numpy(start).cuda()
+    pg.degrid(p, k, dev(g), out=acc, accumulate=True)
+    assert rel(host(acc), start.astype(np.complex128) + want) < TOL
 
 
 def test_c2_degrid_parity(c2_case):
