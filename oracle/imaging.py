@@ -10,7 +10,7 @@ the real part divided by the weight sum (natural weighting).
 import numpy as np
 
 from .geometry import n_minus_one, pixel_coords
-from .mueller import jones_field_to_pixels, mueller_from_jones, stokes_matrix, stokes_mueller
+from .mueller import mueller_from_jones, stokes_matrix, stokes_mueller
 from .pswf import aa_pixels
 
 
@@ -70,8 +70,3 @@ def dft_image(geom, uvw, vis, weight_sum, phi_pixels=None) -> np.ndarray:
         return acc.real / weight_sum
     return np.einsum("qcyx,cyx->qyx", phi_pixels, acc).real / weight_sum
 
-
-def jones_pixels_mueller_stokes(jones, convention: str = "iau") -> np.ndarray:
-    """M^S per pixel from a [2][2][rows][cols] Jones field, [rows][cols][4][4]."""
-    s = stokes_matrix(convention)
-    return stokes_mueller(mueller_from_jones(jones_field_to_pixels(jones)), s)

@@ -132,3 +132,64 @@ def test_predict_transform_is_adjoint_of_image_transform():
     img = imaging.image_from_grid(g, gr, 1.0)  # Re(F gr) / (AA AA)
     rhs = np.vdot(imaging.grid_from_model(g, model), gr).real  # <F^H (model / AA AA), gr>
     assert np.sum(img * model) == pytest.approx(rhs, rel=1e-10)
+
+
+# dft_image with per-pixel screens Phi_qc(l, m): the image is Re sum_c Phi_qc(l, m) A_c(l, m) / weight_sum,
+# A_c the direct transform of correlation c.  The pins below catch a transposed Mueller index (q, c),
+# screens applied at transposed pixels (y, x), a conjugated screen and a dropped imaginary part.
+
+def _small_geom(n=16):
+    return synth.Geometry(n=n, cell=0.05 / n, os=4, w_planes=np.zeros(1), support=np.array([7]), mk=n)
+
+
+def test_dft_image_single_visibility_constant_screen_is_a_cosine_image():
+    """One visibility V_c at (u, v, w) with a constant complex 4x4 screen A:
+    I_q(l, m) = sum_c |A_qc V_c| cos(arg(A_qc V_c) - 2 pi (u l + v m + w (n - 1)))."""
+    g = _small_geom()
+    rng = np.random.default_rng(31)
+    a = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    vis = (rng.standard_normal(4) + 1j * rng.standard_normal(4))[None]
+    u, v, w = 37.0, -12.5, 80.0
+    phi = np.broadcast_to(a[:, :, None, None], (4, 4, g.n, g.n))
+    img = imaging.dft_image(g, np.array([[u, v, w]]), vis, 2.0, phi_pixels=phi)
+    x = (np.arange(g.n) - g.n // 2) * g.cell
+    mm, ll = np.meshgrid(x, x, indexing="ij")
+    nm1 = -(ll ** 2 + mm ** 2) / (1 + np.sqrt(1 - ll ** 2 - mm ** 2))
+    theta = 2 * np.pi * (u * ll + v * mm + w * nm1)
+    for q in range(4):
+        want = sum(abs(a[q, c] * vis[0, c]) * np.cos(np.angle(a[q, c] * vis[0, c]) - theta) for c in range(4)) / 2.0
+        np.testing.assert_allclose(img[q], want, rtol=0, atol=1e-12)
+
+
+def test_dft_image_screen_combines_correlation_images_linearly():
+    """Re(A acc) = Re(A) Re(acc) - Im(A) Im(acc), with Re(acc) and -Im(acc) the identity-screen images of
+    V and of i V: the screened image follows from two unscreened ones for any non-symmetric A."""
+    g = _small_geom()
+    rng = np.random.default_rng(32)
+    uvw = np.stack([rng.uniform(-60, 60, 9), rng.uniform(-60, 60, 9), rng.uniform(-100, 100, 9)], 1)
+    vis = rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4))
+    a = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    phi = np.broadcast_to(a[:, :, None, None], (4, 4, g.n, g.n))
+    got = imaging.dft_image(g, uvw, vis, 3.0, phi_pixels=phi)
+    re_acc = imaging.dft_image(g, uvw, vis, 3.0)          # Re(acc_c) / 3
+    m_im_acc = imaging.dft_image(g, uvw, 1j * vis, 3.0)  # Re(i acc_c) / 3 = -Im(acc_c) / 3
+    want = np.einsum("qc,cyx->qyx", a.real, re_acc) + np.einsum("qc,cyx->qyx", a.imag, m_im_acc)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+def test_dft_image_screen_is_applied_at_its_own_pixel():
+    """With one visibility at the origin every A_c(l, m) equals V_c, so the image is Re(Phi_qc(i, j) V_c):
+    a screen that varies along columns only (or rows only) must come out unchanged in layout."""
+    g = _small_geom()
+    rng = np.random.default_rng(33)
+    vis = np.array([[1.0 + 0.5j, -0.25j, 2.0, 0.75 - 1j]])
+    col = np.arange(g.n, dtype=np.float64)
+    phi = np.zeros((4, 4, g.n, g.n), dtype=np.complex128)
+    phi[0, 2] = col[None, :]                 # varies with j (l)
+    phi[3, 1] = 1j * col[:, None]            # varies with i (m)
+    phi[1, 0] = rng.standard_normal((g.n, g.n))
+    img = imaging.dft_image(g, np.zeros((1, 3)), vis, 1.0, phi_pixels=phi)
+    np.testing.assert_allclose(img[0], np.broadcast_to(col[None, :] * 2.0, (g.n, g.n)), atol=1e-12)
+    np.testing.assert_allclose(img[3], np.broadcast_to((1j * col[:, None] * (-0.25j)).real, (g.n, g.n)), atol=1e-12)
+    np.testing.assert_allclose(img[1], phi[1, 0].real * 1.0, atol=1e-12)
+    np.testing.assert_allclose(img[2], 0.0, atol=1e-12)
