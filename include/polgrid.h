@@ -244,6 +244,8 @@ typedef struct pg_mlp pg_mlp;
 #define PG_MLP_GY_BF16 8 /* its bfloat16 copy, the operand of the output layer's gradient products */
 #define PG_MLP_GZ 9     /* float [batch][d_1] gradient at the first layer's pre-activation */
 #define PG_MLP_GZ_BF16 10 /* its bfloat16 copy */
+#define PG_MLP_MW 11     /* float [d_in][d_out] Adam first moment of the layer's weights */
+#define PG_MLP_VW 12     /* float [d_in][d_out] Adam second moment of the layer's weights */
 
 int pg_mlp_create(int32_t n_in, int32_t width, int32_t hidden_layers, int64_t n_out, int32_t max_batch,
                   uint64_t seed, void* stream, pg_mlp** out);

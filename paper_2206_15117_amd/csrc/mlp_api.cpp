@@ -204,6 +204,8 @@ int pg_mlp_copy(const pg_mlp* m, int32_t what, int32_t layer, void* dst, void* s
     case PG_MLP_GY_BF16: src = m->gy_bf.p; bytes = 2 * B * m->n_out; break;
     case PG_MLP_GZ: src = m->gz.p; bytes = 4 * B * m->dims[1]; break;
     case PG_MLP_GZ_BF16: src = m->gz_bf.p; bytes = 2 * B * m->dims[1]; break;
+    case PG_MLP_MW: src = ly.mw.p; bytes = 4 * din * dout; break;
+    case PG_MLP_VW: src = ly.vw.p; bytes = 4 * din * dout; break;
     default: return fail(PG_EINVAL, "unknown quantity");
   }
   PGM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)), "copy");

@@ -177,7 +177,8 @@ def _geometry_struct(geom):
     return g, (w, s, t)
 
 
-MLP_W, MLP_W_BF16, MLP_B, MLP_GW, MLP_GB, MLP_ACT, MLP_PRE, MLP_GY, MLP_GY_BF16, MLP_GZ, MLP_GZ_BF16 = range(11)
+(MLP_W, MLP_W_BF16, MLP_B, MLP_GW, MLP_GB, MLP_ACT, MLP_PRE, MLP_GY, MLP_GY_BF16, MLP_GZ, MLP_GZ_BF16, MLP_MW,
+ MLP_VW) = range(13)
 
 
 class Kernels:
@@ -357,6 +358,23 @@ def degrid(p: Plan, k: Kernels, g, out=None, fftshift: bool = False, accumulate:
 
 
 def taper(k: Kernels, inp, out, direction: int, weight_sum: float = 1.0, stream=None):
+    """Taper correction between grid and image (pg_taper).  TAPER_IMAGE: inp complex64 [npol, n, n]
+    (the transformed grid) -> out float32 [npol, n, n]; TAPER_PREDICT: inp float32 [npol, n, n] (the
+    model) -> out complex64 [npol, n, n].  Both contiguous, on one device."""
+    import torch
+
+    if direction == TAPER_IMAGE:
+        want_in, want_out = torch.complex64, torch.float32
+    elif direction == TAPER_PREDICT:
+        want_in, want_out = torch.float32, torch.complex64
+    else:
+        raise ValueError("direction must be TAPER_IMAGE or TAPER_PREDICT")
+    shape = _grid_shape(k)
+    for t, dt, what in ((inp, want_in, "input"), (out, want_out, "output")):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"taper {what} must be a contiguous {dt} tensor of shape {list(shape)}")
+    if inp.device != out.device:
+        raise ValueError("taper input and output must be on the same device")
     _check(lib().pg_taper(k.handle, _ptr(inp), _ptr(out), int(direction), float(weight_sum), _stream(stream)))
     return out
 
@@ -542,7 +560,8 @@ class MLP:
                   MLP_GB: ((dout,), torch.float32), MLP_ACT: ((batch, din), torch.bfloat16),
                   MLP_PRE: ((batch, dout), torch.float32), MLP_GY: ((batch, self.dims[-1]), torch.float32),
                   MLP_GY_BF16: ((batch, self.dims[-1]), torch.bfloat16), MLP_GZ: ((batch, self.dims[1]), torch.float32),
-                  MLP_GZ_BF16: ((batch, self.dims[1]), torch.bfloat16)}
+                  MLP_GZ_BF16: ((batch, self.dims[1]), torch.bfloat16), MLP_MW: ((din, dout), torch.float32),
+                  MLP_VW: ((din, dout), torch.float32)}
         shape, dt = shapes[what]
         out = torch.empty(shape, dtype=dt, device="cuda")
         _check(lib().pg_mlp_copy(self._h, int(what), int(layer), _ptr(out), _stream()))

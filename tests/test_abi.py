@@ -122,11 +122,16 @@ def test_null_handles_are_rejected():
 
 def test_last_error_is_cleared_by_a_successful_call():
     lib = pg.lib()
-    lib.pg_grid(None, None, None, None, 0, None)
+    assert lib.pg_grid(None, None, None, None, 0, None) == pg.EINVAL
     assert lib.pg_last_error().decode()
-    lib.pg_set_allocator(pg.ALLOC_FN(), pg.FREE_FN(), None)
+    # an empty phase rotation validates its arguments and succeeds without touching a device
+    rc = lib.pg_phase_rotate(None, None, 0, 4, 0.0, 0.0, 0.1, 0.1, None, None, None)
+    assert rc == pg.OK
+    assert lib.pg_last_error().decode() == ""
+    # and the next failure sets a fresh message
     d = pg.PgPlanDesc()
     assert lib.pg_plan_info(None, ctypes.byref(d)) == pg.EINVAL
+    assert "non-NULL" in lib.pg_last_error().decode()
 
 
 def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):

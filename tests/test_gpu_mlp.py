@@ -90,6 +90,27 @@ def test_adam_update_matches_oracle():
     assert np.max(np.abs(f64(net.copy(pg.MLP_W, 1)) - want)) < 1e-6
 
 
+def test_adam_three_steps_with_moments_match_oracle():
+    """Steps 1-3 from zero moments, each with that step's gradient: weights and both moments follow
+    the oracle's Adam (bias corrections and decay rates act once the moments are non-zero)."""
+    net = pg.MLP(8, 16, 1, 40, max_batch=8, seed=16)
+    gen = torch.Generator(device="cuda").manual_seed(6)
+    x = torch.randn((8, 8), device="cuda", generator=gen)
+    t = torch.randn((8, 40), device="cuda", generator=gen)
+    w = f64(net.copy(pg.MLP_W, 1))
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for step in range(1, 4):
+        net.train_step(x, t, lr=1e-2, update=True)
+        g = f64(net.copy(pg.MLP_GW, 1))  # the gradient this step's update used
+        w, m, v = omlp.adam_step(w, g, m, v, step, 1e-2)
+        assert np.max(np.abs(f64(net.copy(pg.MLP_MW, 1)) - m)) <= 1e-6 * max(np.max(np.abs(m)), 1e-30), step
+        assert np.max(np.abs(f64(net.copy(pg.MLP_VW, 1)) - v)) <= 1e-5 * max(np.max(np.abs(v)), 1e-30), step
+        assert np.max(np.abs(f64(net.copy(pg.MLP_W, 1)) - w)) < 1e-6, step
+        # continue from the device's state so float32 rounding does not accumulate across steps
+        w, m, v = f64(net.copy(pg.MLP_W, 1)), f64(net.copy(pg.MLP_MW, 1)), f64(net.copy(pg.MLP_VW, 1))
+
+
 def test_training_reduces_loss():
     net = pg.MLP(20, 64, 3, 2048, max_batch=64, seed=15)
     gen = torch.Generator(device="cuda").manual_seed(5)
