@@ -11,6 +11,8 @@
 #include "common.hpp"
 #include "mlp.hpp"
 
+#include <cmath>
+
 namespace pg {
 namespace {
 
@@ -150,12 +152,12 @@ __global__ void colsum_kernel(const float* __restrict__ g, int64_t rows, int64_t
 
 __global__ void adam_kernel(float* __restrict__ w, uint16_t* __restrict__ w_bf, const float* __restrict__ g,
                             float* __restrict__ m, float* __restrict__ v, int64_t n, float lr, float b1, float b2,
-                            float eps, float c1, float c2) {
+                            float omb1, float omb2, float eps, float c1, float c2) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
@@ -233,11 +235,15 @@ hipError_t mlp_colsum(const float* g, int64_t rows, int64_t cols, float* out, hi
   return hipGetLastError();
 }
 
-hipError_t mlp_adam(float* w, uint16_t* w_bf, const float* g, float* m, float* v, int64_t n, float lr, float b1,
-                    float b2, float eps, int64_t step, hipStream_t s) {
-  const float c1 = 1.0f / (1.0f - powf(b1, static_cast<float>(step)));
-  const float c2 = 1.0f / (1.0f - powf(b2, static_cast<float>(step)));
-  hipLaunchKernelGGL(adam_kernel, grid_1d(n), dim3(256), 0, s, w, w_bf, g, m, v, n, lr, b1, b2, eps, c1, c2);
+// The decay rates, their complements and the bias corrections are formed in float64 on the host and
+// rounded once: 1 - 0.999f in float32 is 1.3e-5 away from 0.001, which the second moment would carry.
+hipError_t mlp_adam(float* w, uint16_t* w_bf, const float* g, float* m, float* v, int64_t n, float lr, double b1,
+                    double b2, double eps, int64_t step, hipStream_t s) {
+  const float c1 = static_cast<float>(1.0 / (1.0 - std::pow(b1, static_cast<double>(step))));
+  const float c2 = static_cast<float>(1.0 / (1.0 - std::pow(b2, static_cast<double>(step))));
+  hipLaunchKernelGGL(adam_kernel, grid_1d(n), dim3(256), 0, s, w, w_bf, g, m, v, n, lr, static_cast<float>(b1),
+                     static_cast<float>(b2), static_cast<float>(1.0 - b1), static_cast<float>(1.0 - b2),
+                     static_cast<float>(eps), c1, c2);
   return hipGetLastError();
 }
 

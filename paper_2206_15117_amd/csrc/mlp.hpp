@@ -12,8 +12,8 @@ hipError_t mlp_silu_back(const float* gact, const float* z, int64_t n, float* gp
 hipError_t mlp_loss(const float* y, const float* t, int64_t cols, int batch, float* grad, uint16_t* grad_bf,
                     float* loss, hipStream_t s);
 hipError_t mlp_colsum(const float* g, int64_t rows, int64_t cols, float* out, hipStream_t s);
-hipError_t mlp_adam(float* w, uint16_t* w_bf, const float* g, float* m, float* v, int64_t n, float lr, float b1,
-                    float b2, float eps, int64_t step, hipStream_t s);
+hipError_t mlp_adam(float* w, uint16_t* w_bf, const float* g, float* m, float* v, int64_t n, float lr, double b1,
+                    double b2, double eps, int64_t step, hipStream_t s);
 hipError_t mlp_to_bf16(const float* x, int64_t n, uint16_t* out, hipStream_t s);
 hipError_t mlp_init_uniform(float* w, int64_t n, uint64_t seed, float a, hipStream_t s);
 struct CellScale {

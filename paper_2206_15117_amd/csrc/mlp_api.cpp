@@ -174,9 +174,9 @@ int pg_mlp_train_step(pg_mlp* m, const float* x, const float* target, int32_t ba
       auto& ly = m->layers[l];
       const int64_t nw = m->dims[l] * m->dims[l + 1];
       PGM_HIP(pg::mlp_adam(ly.w.as<float>(), ly.w_bf.as<uint16_t>(), ly.gw.as<float>(), ly.mw.as<float>(),
-                           ly.vw.as<float>(), nw, lr, 0.9f, 0.999f, 1e-8f, m->step, s), "adam");
+                           ly.vw.as<float>(), nw, lr, 0.9, 0.999, 1e-8, m->step, s), "adam");
       PGM_HIP(pg::mlp_adam(ly.b.as<float>(), nullptr, ly.gb.as<float>(), ly.mb.as<float>(), ly.vb.as<float>(),
-                           m->dims[l + 1], lr, 0.9f, 0.999f, 1e-8f, m->step, s), "adam");
+                           m->dims[l + 1], lr, 0.9, 0.999, 1e-8, m->step, s), "adam");
     }
   }
   if (loss_out) PGM_HIP(hipMemcpyAsync(loss_out, m->loss.p, 4, hipMemcpyDeviceToDevice, s), "copy loss");
