@@ -281,6 +281,20 @@ int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n,
               float threshold, int32_t psf_patch, int32_t max_iter, int32_t* comp_pos, float* comp_val, float* model,
               int32_t* n_comp, void* stream);
 
+/* pg_hogbom without any device allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, results and
+ * kernels as pg_hogbom; the scratch pg_hogbom allocates per call (iteration state and one 64-bit
+ * peak slot per iteration) is instead a fixed device array of the library, 256 + 8 x
+ * PG_HOGBOM_STATIC_MAX_ITER bytes (about 512 KiB) on each GPU it runs on, held until the process
+ * ends.  Every call on one GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams or threads) race; each call clears the part it uses before its first iteration.  Only
+ * kernel launches are enqueued (no hipMalloc, hipFree, memset or copy).  Errors: as pg_hogbom, and
+ * PG_EINVAL when max_iter exceeds PG_HOGBOM_STATIC_MAX_ITER. */
+#define PG_HOGBOM_STATIC_MAX_ITER 65536
+int pg_hogbom_noalloc(float* residual, const float* psf, const uint8_t* mask, int32_t n, int32_t npol, float gain,
+                      float threshold, int32_t psf_patch, int32_t max_iter, int32_t* comp_pos, float* comp_val,
+                      float* model, int32_t* n_comp, void* stream);
+
 /* ------------------------------------------------------------------ batched launch
  * Many fields (channels or mosaic pointings, each with its own plan, kernels, visibilities and
  * grid; uneven visibility counts) gridded or degridded by ONE launch over every (field, work

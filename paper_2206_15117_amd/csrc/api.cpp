@@ -578,10 +578,8 @@ int pg_weight_normalise(float* img, const float* weight, int32_t n, int32_t npol
   return PG_OK;
 }
 
-int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n, int32_t npol, float gain,
-              float threshold, int32_t psf_patch, int32_t max_iter, int32_t* comp_pos, float* comp_val, float* model,
-              int32_t* n_comp, void* stream) {
-  g_error.clear();
+static int check_hogbom(const float* residual, const float* psf, const int32_t* comp_pos, const float* comp_val,
+                 const int32_t* n_comp, int32_t n, int32_t npol, float gain, float threshold, int32_t max_iter) {
   if (!residual || !psf || !comp_pos || !comp_val || !n_comp)
     return fail(PG_EINVAL, "residual, psf, comp_pos, comp_val and n_comp must be non-NULL");
   if (n < 2 || n > 16384 || (n & 1)) return fail(PG_EINVAL, "n must be even and in [2, 16384]");
@@ -589,6 +587,15 @@ int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n,
   if (!(gain > 0.0f && gain <= 1.0f)) return fail(PG_EINVAL, "gain must be in (0, 1]");
   if (!(threshold >= 0.0f) || !std::isfinite(threshold)) return fail(PG_EINVAL, "threshold must be finite and >= 0");
   if (max_iter < 0 || max_iter > (1 << 20)) return fail(PG_EINVAL, "max_iter must be in [0, 2^20]");
+  return PG_OK;
+}
+
+int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n, int32_t npol, float gain,
+              float threshold, int32_t psf_patch, int32_t max_iter, int32_t* comp_pos, float* comp_val, float* model,
+              int32_t* n_comp, void* stream) {
+  g_error.clear();
+  const int rc = check_hogbom(residual, psf, comp_pos, comp_val, n_comp, n, npol, gain, threshold, max_iter);
+  if (rc != PG_OK) return rc;
   const int patch = (psf_patch <= 0 || psf_patch > n) ? n : psf_patch;
   hipStream_t s = static_cast<hipStream_t>(stream);
   try {
@@ -601,6 +608,26 @@ int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n,
   } catch (...) {
     return fail(PG_ENOMEM, "exception in hogbom");
   }
+  return PG_OK;
+}
+
+int pg_hogbom_noalloc(float* residual, const float* psf, const uint8_t* mask, int32_t n, int32_t npol, float gain,
+                      float threshold, int32_t psf_patch, int32_t max_iter, int32_t* comp_pos, float* comp_val,
+                      float* model, int32_t* n_comp, void* stream) {
+  g_error.clear();
+  const int rc = check_hogbom(residual, psf, comp_pos, comp_val, n_comp, n, npol, gain, threshold, max_iter);
+  if (rc != PG_OK) return rc;
+  if (max_iter > PG_HOGBOM_STATIC_MAX_ITER)
+    return fail(PG_EINVAL, "max_iter exceeds PG_HOGBOM_STATIC_MAX_ITER (" +
+                               std::to_string(PG_HOGBOM_STATIC_MAX_ITER) + ") for pg_hogbom_noalloc");
+  const int patch = (psf_patch <= 0 || psf_patch > n) ? n : psf_patch;
+  void* scratch = nullptr;
+  size_t bytes = 0;
+  PG_HIP(hogbom_static_scratch(&scratch, &bytes), "hogbom_noalloc scratch address");
+  if (256 + 8 * static_cast<size_t>(std::max(max_iter, 1)) > bytes) return fail(PG_EINVAL, "scratch too small");
+  PG_HIP(launch_hogbom(residual, psf, mask, n, npol, gain, threshold, patch, max_iter, comp_pos, comp_val, model,
+                       n_comp, scratch, static_cast<hipStream_t>(stream)),
+         "hogbom_noalloc");
   return PG_OK;
 }
 

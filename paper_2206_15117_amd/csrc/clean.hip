@@ -13,6 +13,9 @@
 // then difference rounded) so that the float32 reference reproduces it bit for bit.
 #include "common.hpp"
 
+#include <mutex>
+#include <vector>
+
 namespace pg {
 namespace {
 
@@ -114,7 +117,33 @@ __global__ void clean_init_kernel(CleanState* st, unsigned long long* slots, int
 
 __global__ void clean_count_kernel(const CleanState* st, int32_t* n_comp) { *n_comp = st->ncomp; }
 
+// Scratch of the allocation-free entry point: the iteration state (256 B) and one 64-bit peak
+// slot per iteration, for at most kStaticMaxIter iterations.  Each GPU holds its own copy; host
+// code reaches it only through the address hipGetSymbolAddress returns on that device.
+constexpr size_t kStaticScratchBytes = 256 + 8 * static_cast<size_t>(PG_HOGBOM_STATIC_MAX_ITER);
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_static_mu;
+std::vector<void*> g_static_ptr;  // per device, looked up once with that device current
+
 }  // namespace
+
+hipError_t hogbom_static_scratch(void** out, size_t* bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (static_cast<size_t>(dev) >= g_static_ptr.size()) g_static_ptr.resize(dev + 1, nullptr);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_static_ptr[dev] = ptr;
+  }
+  *out = g_static_ptr[dev];
+  *bytes = kStaticScratchBytes;
+  return hipSuccess;
+}
 
 hipError_t launch_hogbom(float* residual, const float* psf, const uint8_t* mask, int n, int npol, float gain,
                          float threshold, int patch, int max_iter, int32_t* comp_pos, float* comp_val, float* model,

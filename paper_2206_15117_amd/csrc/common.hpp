@@ -202,6 +202,8 @@ hipError_t launch_taper(const pg_kernels* k, const void* in, void* out, int dire
 hipError_t launch_hogbom(float* residual, const float* psf, const uint8_t* mask, int n, int npol, float gain,
                          float threshold, int patch, int max_iter, int32_t* comp_pos, float* comp_val, float* model,
                          int32_t* n_comp, void* scratch, hipStream_t s);
+// Device address (on the current device) and size of the fixed scratch array of pg_hogbom_noalloc.
+hipError_t hogbom_static_scratch(void** out, size_t* bytes);
 hipError_t launch_batch_grid(const pg_batch* b, int flags, hipStream_t s);
 hipError_t launch_batch_degrid(const pg_batch* b, int flags, hipStream_t s);
 

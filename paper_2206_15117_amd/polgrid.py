@@ -86,6 +86,8 @@ EXPORTS = {
     "pg_kernels_alloc": (c_int, [POINTER(PgKernelSpec), c_void_p, POINTER(c_void_p)]),
     "pg_hogbom": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, ctypes.c_float, c_int32,
                           c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pg_hogbom_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, ctypes.c_float,
+                                  c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pg_kernels_export": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "pg_kernels_import": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "pg_mlp_create": (c_int, [c_int32, c_int32, c_int32, c_int64, c_int32, ctypes.c_uint64, c_void_p,
@@ -466,9 +468,13 @@ def weight_normalise(img, weight, min_weight: float, stream=None):
     return img
 
 
+HOGBOM_STATIC_MAX_ITER = 65536
+
+
 def hogbom(residual, psf, mask=None, gain: float = 0.1, threshold: float = 0.0, max_iter: int = 1000,
-           psf_patch: int = 0, model=None, stream=None):
-    """Hogbom minor cycle on the device (pg_hogbom): residual float32 [npol, n, n] is cleaned in
+           psf_patch: int = 0, model=None, stream=None, noalloc: bool = False):
+    """Hogbom minor cycle on the device (pg_hogbom, or pg_hogbom_noalloc with noalloc=True, whose
+    scratch is the library's fixed device array): residual float32 [npol, n, n] is cleaned in
     place; returns (component pixel indices int32 [m], component values float32 [m, npol])."""
     import torch
 
@@ -485,9 +491,10 @@ def hogbom(residual, psf, mask=None, gain: float = 0.1, threshold: float = 0.0, 
     pos = torch.empty(max(max_iter, 1), dtype=torch.int32, device=residual.device)
     val = torch.empty((max(max_iter, 1), npol), dtype=torch.float32, device=residual.device)
     cnt = torch.zeros(1, dtype=torch.int32, device=residual.device)
-    _check(lib().pg_hogbom(_ptr(residual), _ptr(psf), _ptr(mask), int(n), int(npol), ctypes.c_float(gain),
-                           ctypes.c_float(threshold), int(psf_patch), int(max_iter), _ptr(pos), _ptr(val),
-                           _ptr(model), _ptr(cnt), _stream(stream)))
+    fn = lib().pg_hogbom_noalloc if noalloc else lib().pg_hogbom
+    _check(fn(_ptr(residual), _ptr(psf), _ptr(mask), int(n), int(npol), ctypes.c_float(gain),
+              ctypes.c_float(threshold), int(psf_patch), int(max_iter), _ptr(pos), _ptr(val), _ptr(model), _ptr(cnt),
+              _stream(stream)))
     m = int(cnt.item())
     return pos[:m], val[:m]
 
