@@ -20,6 +20,8 @@ on, written in float64 / complex128 with numpy and scipy primitives:
              direct Fourier transforms used as truth
   plan       the visibility binning (plane, uv tile, oversampling phase)
   mlp        FP64 forward/backward of the kernel-surrogate network
+  uvmosaic   UV-domain mosaics: per-field beam kernels on one grid and the
+             image correction gamma of Eq. 1 (Sec. 2.2)
 
 Readings of passages the paper leaves open are listed in the module that
 takes them.  Functions without an independent pin say "parity unpinned".

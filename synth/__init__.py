@@ -168,6 +168,29 @@ class GaussianLeakageBeam:
         return j
 
 
+@dataclass
+class OffsetBeam:
+    """A beam model centred on a mosaic pointing at (l0, m0) of the common frame: the Jones matrix
+    and the power beam E^2 at (l, m) are those of `base` at (l - l0, m - m0)."""
+
+    base: GaussianLeakageBeam
+    l0: float
+    m0: float
+
+    def jones(self, l, m) -> np.ndarray:
+        return self.base.jones(np.asarray(l) - self.l0, np.asarray(m) - self.m0)
+
+    def power(self, l, m) -> np.ndarray:
+        return np.abs(self.jones(l, m)[..., 0, 0]) ** 2
+
+
+def power_on_pixels(beam, n: int, cell: float) -> np.ndarray:
+    """float64 [n (m, rows)][n (l, columns)] power beam at the image pixel centres."""
+    x = (np.arange(n) - n // 2) * cell
+    mm, ll = np.meshgrid(x, x, indexing="ij")
+    return beam.power(ll, mm)
+
+
 def seeded_leakage_beam(theta, rng, level=0.01) -> GaussianLeakageBeam:
     def cn(k):
         return (rng.standard_normal(k) + 1j * rng.standard_normal(k)) / math.sqrt(2.0)
