@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-scale", action="store_true", help="skip the 20M-row major-cycle section")
     ap.add_argument("--no-clean", action="store_true", help="skip the Cotton-Schwab clean section")
     ap.add_argument("--no-mosaic", action="store_true", help="skip the 7-field mosaic section")
+    ap.add_argument("--network-only", action="store_true",
+                    help="time only the kernel network's products (forward at batch 256 and 2048, one training "
+                         "step) on the 24 -> 3 x 256 -> 294912 shape and print that section as the JSON line")
     ap.add_argument("--surrogate-kernels", type=int, default=200_000,
                     help="teacher kernels the network is trained on")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -91,6 +94,9 @@ def main():
 
     torch.cuda.set_device(0)
     pg.use_torch_allocator(True)
+    if args.network_only:
+        print(json.dumps({"network": bench_network()}), flush=True)
+        return
     variant = {"auto": 0, "atomic": pg.VARIANT_ATOMIC, "banded": pg.VARIANT_BANDED}[args.grid_variant]
     from paper_2206_15117_amd import autotune
 
@@ -225,6 +231,7 @@ def main():
         log(f"mosaic step timed: {out['mosaic']['ms_per_step']:.1f} ms")
     if not args.no_surrogate:
         torch.cuda.empty_cache()
+        out["network"] = bench_network()
         out["surrogate"] = bench_surrogate(args.surrogate_kernels)
         log("learned-kernel section done")
     if not args.no_cpu_baseline:
@@ -565,6 +572,45 @@ def bench_mosaic(steps, warmup):
             "phase_rotate_roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                                       "achieved": w.nvis * 112 / (ms["phase_rotate"] * 1e-3) / 1e9,
                                       "frac": w.nvis * 112 / (ms["phase_rotate"] * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
+def bench_network(batches=(256, 2048), reps=10):
+    """The kernel network alone at the surrogate's shape (24 features -> 3 x 256 SiLU -> 294912
+    outputs, random weights): whole-forward time per batch (HIP events), kernels per second, and
+    the forward's flop rate; one training step (forward, loss, backward, Adam) at batch 256."""
+    import torch
+
+    from paper_2206_15117_amd import polgrid as pg
+
+    out = {"shape": "24 -> 3 x 256 SiLU -> 294912, bf16 products with float32 accumulation"}
+    for b in batches:
+        net = pg.MLP(24, 256, 3, 294912, max_batch=b, seed=3)
+        x = torch.randn((b, 24), device="cuda")
+        y = torch.empty((b, 294912), device="cuda")
+        net.forward(x, out=y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            net.forward(x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        flops = 2 * b * (24 * 256 + 2 * 256 * 256 + 256 * 294912)
+        out[f"forward_batch_{b}"] = {"ms": ms, "kernels_per_s": b / (ms * 1e-3), "tflops": flops / (ms * 1e-3) / 1e12}
+        if b == batches[0]:
+            t = torch.randn((b, 294912), device="cuda")
+            net.train_step(x, t, lr=1e-4)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(3):
+                net.train_step(x, t, lr=1e-4)
+            e1.record()
+            torch.cuda.synchronize()
+            out[f"train_step_batch_{b}_ms"] = e0.elapsed_time(e1) / 3
+        del net, y
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_surrogate(n_kernels):

@@ -3,11 +3,10 @@
 //
 //   h_0 = x (features), h_l = SiLU(h_{l-1} W_l + b_l) for the hidden layers, y = h_L W_out + b_out.
 //
-// GEMM: C[M][N] (float) (+)= A[M][K] B[K][N] with bf16 operands given by arbitrary strides, so the
-// forward product, the input gradient (B = W^T) and the weight gradient (A = h^T) share one
-// kernel.  64x64 output tile per 256-thread workgroup, four waves of 32x32, K in steps of 32
-// staged through LDS ([m][k] for A and [n][k] for B so each lane's four consecutive k values are
-// one 8-byte read), v_mfma_f32_32x32x8_bf16, optional split-K with float atomics.
+// GEMMs (C (+)= A B) run on the matrix cores with bf16 operands and float accumulation; the forward
+// product, the input gradient (B = W^T) and the weight gradient (A = h^T) share one kernel that
+// takes each operand either k-contiguous or row-contiguous.  Bias and SiLU are fused into the
+// forward products' epilogue.
 #include "common.hpp"
 #include "mlp.hpp"
 
@@ -27,71 +26,170 @@ __device__ inline uint16_t f2bf(float f) {  // round to nearest even
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
-constexpr int TM = 64, TN = 64, TK = 32, KP = TK + 4;  // LDS row pitch in bf16 (8-byte aligned rows)
+// GEMM C[M][N] (+)= A[M][K] B[K][N], bf16 operands, float accumulation on the matrix cores
+// (v_mfma_f32_32x32x16_bf16).  A is given k-contiguous ([M][K], row stride lda) or m-contiguous
+// ([K][M]); B k-contiguous ([N][K], row stride ldb) or n-contiguous ([K][N]).  Each 256-thread
+// workgroup computes a 128 x 128 tile, each wave 64 x 64 (2 x 2 MFMA tiles of 32 x 32).  Tiles of
+// 128 rows x 32 k of both operands are staged in LDS as [row][k] (k-contiguous rows of 40 bf16,
+// the four 8-element k chunks of a row XOR-swizzled by row / 8 so the 16-byte operand reads of 8
+// lanes cover all 32 banks and the transposing stores spread over 16), double-buffered: the next
+// k-step's global loads are in flight while the current one feeds the matrix cores, and one
+// barrier per k-step separates the buffers.  Row-contiguous operands are transposed while being
+// written into LDS.  The epilogue (store, accumulate, atomic add for a split contraction, or store
+// with bias and optionally SiLU in bf16) is a template parameter.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A,
-                                                        int64_t sam, int64_t sak, const uint16_t* __restrict__ B,
-                                                        int64_t sbk, int64_t sbn, float* __restrict__ C, int64_t ldc,
-                                                        int ksplit, int accumulate) {
-  __shared__ __attribute__((aligned(16))) uint16_t as[TM][KP];
-  __shared__ __attribute__((aligned(16))) uint16_t bs[TN][KP];
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int kb = blockIdx.z * ksplit, ke = min(K, kb + ksplit);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f32x16 acc;
+constexpr int BM = 128, BN = 128, BK = 32, LP = BK + 8;
+enum GemmEpi { kEpiStore, kEpiAccumulate, kEpiAtomic, kEpiBias, kEpiBiasSilu };
+
+// bf16 element offset of (row, k) in a staged tile: chunk k / 8 swizzled by (row / 8) mod 4
+__device__ __forceinline__ int lds_at(int row, int k) { return row * LP + ((((k >> 3) ^ (row >> 3)) & 3) << 3) + (k & 7); }
+
+// One operand tile (128 rows x BK) into registers: two 8-element chunks per thread.  k-contiguous
+// sources: thread chunk c is row c / 4, k chunk c % 4.  Row-contiguous sources: c is k = c % 32,
+// rows 8 (c / 32) .. + 7, so the lanes of a wave write 32 different k of one row into LDS.
+template <bool KCONTIG, bool VEC>
+struct TileLoader {
+  u32x4 r[2];
+  __device__ void load(const uint16_t* __restrict__ X, int64_t ld, int rows, int K, int row0, int k0, int tid) {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = kb; k0 < ke; k0 += TK) {
-    for (int e = tid; e < TM * TK; e += 256) {
-      const int mm = e / TK, kk = e % TK;
-      const int gm = m0 + mm, gk = k0 + kk;
-      as[mm][kk] = (gm < M && gk < ke) ? A[gm * sam + gk * sak] : uint16_t(0);
-    }
-    for (int e = tid; e < TN * TK; e += 256) {
-      const int nn = e % TN, kk = e / TN;
-      const int gn = n0 + nn, gk = k0 + kk;
-      bs[nn][kk] = (gn < N && gk < ke) ? B[gk * sbk + gn * sbn] : uint16_t(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 8) {
-      const int ko = kk + 4 * (lane >> 5);
-      bf16x4 a, b;
-      __builtin_memcpy(&a, &as[wm + (lane & 31)][ko], 8);
-      __builtin_memcpy(&b, &bs[wn + (lane & 31)][ko], 8);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  // accumulator r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32 of the wave tile
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    const int j = n0 + wn + (lane & 31);
-    if (i < M && j < N) {
-      float* c = C + static_cast<int64_t>(i) * ldc + j;
-      if (gridDim.z > 1) {
-        unsafeAtomicAdd(c, acc[r]);
-      } else if (accumulate) {
-        *c += acc[r];
+    for (int h = 0; h < 2; ++h) {
+      const int c = tid + h * 256;
+      const int row = KCONTIG ? c >> 2 : (c >> 5) * 8;
+      const int k = KCONTIG ? (c & 3) * 8 : c & 31;
+      const int gr = row0 + row, gk = k0 + k;
+      const bool whole = VEC && (KCONTIG ? (gr < rows && gk + 8 <= K) : (gk < K && gr + 8 <= rows));
+      if (whole) {
+        const uint16_t* p = KCONTIG ? X + static_cast<int64_t>(gr) * ld + gk : X + static_cast<int64_t>(gk) * ld + gr;
+        r[h] = *reinterpret_cast<const u32x4*>(p);
       } else {
-        *c = acc[r];
+        uint16_t e[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int rr = KCONTIG ? gr : gr + i, kk = KCONTIG ? gk + i : gk;
+          e[i] = (rr < rows && kk < K) ? X[KCONTIG ? static_cast<int64_t>(rr) * ld + kk : static_cast<int64_t>(kk) * ld + rr]
+                                       : uint16_t(0);
+        }
+        __builtin_memcpy(&r[h], e, 16);
       }
     }
   }
+  __device__ void store(uint16_t* S, int tid) const {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = tid + h * 256;
+      if constexpr (KCONTIG) {
+        *reinterpret_cast<u32x4*>(S + lds_at(c >> 2, (c & 3) * 8)) = r[h];
+      } else {
+        uint16_t e[8];
+        __builtin_memcpy(e, &r[h], 16);
+        const int k = c & 31, row = (c >> 5) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) S[lds_at(row + i, k)] = e[i];
+      }
+    }
+  }
+};
+
+template <bool A_K, bool B_K, bool VEC, int EPI>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, const uint16_t* __restrict__ A,
+                                                        int64_t lda, const uint16_t* __restrict__ B, int64_t ldb,
+                                                        float* __restrict__ C, int64_t ldc, int ksplit,
+                                                        const float* __restrict__ bias, uint16_t* __restrict__ act) {
+  __shared__ __attribute__((aligned(16))) uint16_t as[2][BM * LP];
+  __shared__ __attribute__((aligned(16))) uint16_t bs[2][BN * LP];
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int kb = blockIdx.z * ksplit, ke = min(K, kb + ksplit);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  TileLoader<A_K, VEC> la;
+  TileLoader<B_K, VEC> lb;
+  la.load(A, lda, M, ke, m0, kb, tid);
+  lb.load(B, ldb, N, ke, n0, kb, tid);
+  la.store(as[0], tid);
+  lb.store(bs[0], tid);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) {
+      la.load(A, lda, M, ke, m0, k0 + BK, tid);
+      lb.load(B, ldb, N, ke, n0, k0 + BK, tid);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      const int ko = ks + 8 * (lane >> 5);
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        __builtin_memcpy(&a[i], &as[cur][lds_at(wm + i * 32 + (lane & 31), ko)], 16);
+        __builtin_memcpy(&b[i], &bs[cur][lds_at(wn + i * 32 + (lane & 31), ko)], 16);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      la.store(as[cur ^ 1], tid);
+      lb.store(bs[cur ^ 1], tid);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  // accumulator r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32 of a 32 x 32 tile
+  const bool inside = m0 + BM <= M && n0 + BN <= N;
+  float bj[2] = {0.0f, 0.0f};
+  if constexpr (EPI == kEpiBias || EPI == kEpiBiasSilu) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 32 + (lane & 31);
+      bj[j] = col < N ? bias[col] : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = n0 + wn + j * 32 + (lane & 31);
+        if (inside || (row < M && col < N)) {
+          float* c = C + static_cast<int64_t>(row) * ldc + col;
+          float v = acc[i][j][r];
+          if constexpr (EPI == kEpiAtomic) {
+            unsafeAtomicAdd(c, v);
+          } else {
+            if constexpr (EPI == kEpiAccumulate) v += *c;
+            if constexpr (EPI == kEpiBias || EPI == kEpiBiasSilu) v += bj[j];
+            *c = v;
+            if constexpr (EPI == kEpiBiasSilu)
+              act[static_cast<int64_t>(row) * ldc + col] = f2bf(__fdividef(v, 1.0f + __expf(-v)));
+          }
+        }
+      }
 }
 
-// y = x + b (row broadcast); a = SiLU(y) in bf16 when silu, else y stays float (output layer)
-__global__ void bias_act_kernel(float* __restrict__ y, const float* __restrict__ b, int64_t rows, int64_t cols, int silu,
-                                uint16_t* __restrict__ act) {
-  const int64_t n = rows * cols;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const float v = y[i] + b[i % cols];
-    y[i] = v;
-    if (silu) act[i] = f2bf(v / (1.0f + __expf(-v)));
-  }
+// Transpose of a bf16 matrix: out[c][r] = in[r][c], in [rows][cols]; 32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void transpose_bf16_kernel(const uint16_t* __restrict__ in, int64_t rows,
+                                                             int64_t cols, uint16_t* __restrict__ out) {
+  __shared__ uint16_t t[32][33];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 32, c0 = static_cast<int64_t>(blockIdx.x) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8)
+    if (r0 + y < rows && c0 + tx < cols) t[y][tx] = in[(r0 + y) * cols + c0 + tx];
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8)
+    if (c0 + y < cols && r0 + tx < rows) out[(c0 + y) * rows + r0 + tx] = t[tx][y];
 }
 
 // grad of SiLU: g_pre = g_act * s (1 + z (1 - s)), s = sigmoid(z); output bf16 for the next GEMMs
@@ -197,25 +295,67 @@ inline dim3 grid_1d(int64_t n) { return dim3(static_cast<unsigned>(std::min<int6
 
 }  // namespace
 
+template <bool A_K, bool B_K, int EPI>
+hipError_t launch_gemm(int M, int N, int K, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, float* C,
+                       int64_t ldc, int ksplit, int nz, const float* bias, uint16_t* act, bool vec, hipStream_t s) {
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, nz);
+  if (vec)
+    hipLaunchKernelGGL((gemm_mfma_kernel<A_K, B_K, true, EPI>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
+                       ldc, ksplit, bias, act);
+  else
+    hipLaunchKernelGGL((gemm_mfma_kernel<A_K, B_K, false, EPI>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
+                       ldc, ksplit, bias, act);
+  return hipGetLastError();
+}
+
+template <bool A_K, bool B_K>
+hipError_t launch_gemm_epi(int M, int N, int K, const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb,
+                           float* C, int64_t ldc, int ksplit, int nz, bool accumulate, const float* bias,
+                           uint16_t* act, bool vec, hipStream_t s) {
+  if (nz > 1)
+    return launch_gemm<A_K, B_K, kEpiAtomic>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, bias, act, vec, s);
+  if (accumulate)
+    return launch_gemm<A_K, B_K, kEpiAccumulate>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, bias, act, vec, s);
+  if (bias && act)
+    return launch_gemm<A_K, B_K, kEpiBiasSilu>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, bias, act, vec, s);
+  if (bias) return launch_gemm<A_K, B_K, kEpiBias>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, bias, act, vec, s);
+  return launch_gemm<A_K, B_K, kEpiStore>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, bias, act, vec, s);
+}
+
 hipError_t mlp_gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
-                    int64_t sbn, float* C, int64_t ldc, bool accumulate, int split_k, hipStream_t s) {
+                    int64_t sbn, float* C, int64_t ldc, bool accumulate, int split_k, hipStream_t s, const float* bias,
+                    uint16_t* act) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  // each operand needs a unit stride along k or along its row index
+  const bool a_k = sak == 1, b_k = sbk == 1;
+  if (!(a_k || sam == 1) || !(b_k || sbn == 1)) return hipErrorInvalidValue;
+  if (act && !bias) return hipErrorInvalidValue;
+  const int64_t lda = a_k ? sam : sak, ldb = b_k ? sbn : sbk;
   int ksplit = K;
-  if (split_k > 1) ksplit = ((K + split_k - 1) / split_k + TK - 1) / TK * TK;
+  if (split_k > 1) ksplit = ((K + split_k - 1) / split_k + BK - 1) / BK * BK;
   const int nz = (K + ksplit - 1) / ksplit;
-  if (nz > 1 && !accumulate) {  // split-K partial tiles are added atomically onto zero
+  if (nz > 1 && bias) return hipErrorInvalidValue;  // the bias epilogue needs whole sums
+  if (nz > 1 && !accumulate) {  // split-K partial tiles are added atomically onto zero (or onto C)
     hipLaunchKernelGGL(zero_rows_kernel, dim3(M), dim3(256), 0, s, C, ldc, N);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, nz);
-  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, ksplit,
-                     accumulate ? 1 : 0);
-  return hipGetLastError();
+  // 16-byte operand loads need 16-byte aligned rows (bf16 row stride a multiple of 8)
+  const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0) &&
+                   lda % 8 == 0 && ldb % 8 == 0;
+  if (a_k && b_k)
+    return launch_gemm_epi<true, true>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, accumulate, bias, act, vec, s);
+  if (a_k)
+    return launch_gemm_epi<true, false>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, accumulate, bias, act, vec, s);
+  if (b_k)
+    return launch_gemm_epi<false, true>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, accumulate, bias, act, vec, s);
+  return launch_gemm_epi<false, false>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, accumulate, bias, act, vec, s);
 }
 
-hipError_t mlp_bias_act(float* y, const float* b, int64_t rows, int64_t cols, bool silu, uint16_t* act, hipStream_t s) {
-  hipLaunchKernelGGL(bias_act_kernel, grid_1d(rows * cols), dim3(256), 0, s, y, b, rows, cols, silu ? 1 : 0, act);
+hipError_t mlp_transpose_bf16(const uint16_t* in, int64_t rows, int64_t cols, uint16_t* out, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  dim3 grid(static_cast<unsigned>((cols + 31) / 32), static_cast<unsigned>((rows + 31) / 32));
+  hipLaunchKernelGGL(transpose_bf16_kernel, grid, dim3(256), 0, s, in, rows, cols, out);
   return hipGetLastError();
 }
 

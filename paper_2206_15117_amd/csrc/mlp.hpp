@@ -5,9 +5,12 @@
 #include <cstdint>
 
 namespace pg {
+// C (+)= A B; bias (optional, not with a split contraction) adds a row vector, act (optional)
+// receives SiLU(C) in bf16 with C's row stride.
 hipError_t mlp_gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
-                    int64_t sbn, float* C, int64_t ldc, bool accumulate, int split_k, hipStream_t s);
-hipError_t mlp_bias_act(float* y, const float* b, int64_t rows, int64_t cols, bool silu, uint16_t* act, hipStream_t s);
+                    int64_t sbn, float* C, int64_t ldc, bool accumulate, int split_k, hipStream_t s,
+                    const float* bias = nullptr, uint16_t* act = nullptr);
+hipError_t mlp_transpose_bf16(const uint16_t* in, int64_t rows, int64_t cols, uint16_t* out, hipStream_t s);
 hipError_t mlp_silu_back(const float* gact, const float* z, int64_t n, float* gpre, uint16_t* gpre_bf, hipStream_t s);
 hipError_t mlp_loss(const float* y, const float* t, int64_t cols, int batch, float* grad, uint16_t* grad_bf,
                     float* loss, hipStream_t s);

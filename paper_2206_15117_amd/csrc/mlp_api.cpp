@@ -17,6 +17,7 @@ struct pg_mlp {
   std::vector<int64_t> dims;  // d_0 = n_in, d_1..d_hidden = width, d_{hidden+1} = n_out
   struct Layer {
     pg::DevBuf w, w_bf, b, gw, gb, mw, vw, mb, vb;
+    pg::DevBuf w_bft;  // bf16 [d_out][d_in]: the forward product's k-contiguous operand
   };
   std::vector<Layer> layers;          // layers[l] maps d_l -> d_{l+1}
   pg::DevBuf x_bf;                    // [B][n_in] bf16
@@ -40,10 +41,10 @@ int fail(int code, const std::string& m) {
     if (e_ != hipSuccess) return fail(PG_EHIP, std::string(what) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Contraction split for a product whose 64 x 64 output tiles alone cannot fill the GPU: enough
+// Contraction split for a product whose 128 x 128 output tiles alone cannot fill the GPU: enough
 // slices for about 512 workgroups, each slice at least 256 deep.
 int split_for(int64_t M, int64_t N, int64_t K) {
-  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
   if (tiles >= 512) return 1;
   const int64_t split = std::min<int64_t>((512 + tiles - 1) / tiles, K / 256);
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(split, 256)));
@@ -56,11 +57,12 @@ int forward_impl(pg_mlp* m, const float* x, int batch, hipStream_t s) {
   for (int l = 0; l < L; ++l) {
     const int64_t din = m->dims[l], dout = m->dims[l + 1];
     float* z = m->pre[l].as<float>();
-    PGM_HIP(pg::mlp_gemm(batch, static_cast<int>(dout), static_cast<int>(din), a, din, 1, m->layers[l].w_bf.as<uint16_t>(),
-                         dout, 1, z, dout, false, 1, s), "forward gemm");
+    // z = a W + b, and for hidden layers SiLU(z) in bf16, in the product's epilogue
     const bool hidden = l + 1 < L;
-    PGM_HIP(pg::mlp_bias_act(z, m->layers[l].b.as<float>(), batch, dout, hidden, hidden ? m->act[l].as<uint16_t>() : nullptr, s),
-            "bias/activation");
+    PGM_HIP(pg::mlp_gemm(batch, static_cast<int>(dout), static_cast<int>(din), a, din, 1, m->layers[l].w_bft.as<uint16_t>(),
+                         1, din, z, dout, false, 1, s, m->layers[l].b.as<float>(),
+                         hidden ? m->act[l].as<uint16_t>() : nullptr),
+            "forward gemm");
     if (hidden) a = m->act[l].as<uint16_t>();
   }
   m->last_batch = batch;
@@ -98,7 +100,8 @@ int pg_mlp_create(int32_t n_in, int32_t width, int32_t hidden_layers, int64_t n_
   for (int l = 0; l < L; ++l) {
     const int64_t din = m->dims[l], dout = m->dims[l + 1], nw = din * dout;
     auto& ly = m->layers[l];
-    if (!ly.w.alloc(4 * nw, s) || !ly.w_bf.alloc(2 * nw, s) || !ly.b.alloc(4 * dout, s) || !ly.gw.alloc(4 * nw, s) ||
+    if (!ly.w.alloc(4 * nw, s) || !ly.w_bf.alloc(2 * nw, s) || !ly.w_bft.alloc(2 * nw, s) || !ly.b.alloc(4 * dout, s) ||
+        !ly.gw.alloc(4 * nw, s) ||
         !ly.gb.alloc(4 * dout, s) || !ly.mw.alloc(4 * nw, s) || !ly.vw.alloc(4 * nw, s) || !ly.mb.alloc(4 * dout, s) ||
         !ly.vb.alloc(4 * dout, s) || !m->pre[l].alloc(4 * B * dout, s))
       return fail(PG_ENOMEM, "device allocation failed in mlp_create");
@@ -106,6 +109,7 @@ int pg_mlp_create(int32_t n_in, int32_t width, int32_t hidden_layers, int64_t n_
     const float a = static_cast<float>(std::sqrt((l + 1 < L ? 6.0 : 3.0) / static_cast<double>(din)));
     PGM_HIP(pg::mlp_init_uniform(ly.w.as<float>(), nw, seed + (static_cast<uint64_t>(l) << 40), a, s), "init");
     PGM_HIP(pg::mlp_to_bf16(ly.w.as<float>(), nw, ly.w_bf.as<uint16_t>(), s), "init bf16");
+    PGM_HIP(pg::mlp_transpose_bf16(ly.w_bf.as<uint16_t>(), din, dout, ly.w_bft.as<uint16_t>(), s), "init transpose");
     for (pg::DevBuf* z : {&ly.b, &ly.mw, &ly.vw, &ly.mb, &ly.vb, &ly.gb})
       PGM_HIP(pg::launch_fill_zero(z->p, z->bytes, s), "zero");
   }
@@ -175,6 +179,8 @@ int pg_mlp_train_step(pg_mlp* m, const float* x, const float* target, int32_t ba
       const int64_t nw = m->dims[l] * m->dims[l + 1];
       PGM_HIP(pg::mlp_adam(ly.w.as<float>(), ly.w_bf.as<uint16_t>(), ly.gw.as<float>(), ly.mw.as<float>(),
                            ly.vw.as<float>(), nw, lr, 0.9, 0.999, 1e-8, m->step, s), "adam");
+      PGM_HIP(pg::mlp_transpose_bf16(ly.w_bf.as<uint16_t>(), m->dims[l], m->dims[l + 1], ly.w_bft.as<uint16_t>(), s),
+              "adam transpose");
       PGM_HIP(pg::mlp_adam(ly.b.as<float>(), nullptr, ly.gb.as<float>(), ly.mb.as<float>(), ly.vb.as<float>(),
                            m->dims[l + 1], lr, 0.9, 0.999, 1e-8, m->step, s), "adam");
     }
@@ -222,6 +228,8 @@ int pg_mlp_load(pg_mlp* m, int32_t layer, const float* w, const float* b, void* 
   PGM_HIP(hipMemcpyAsync(ly.w.p, w, 4 * nw, hipMemcpyDeviceToDevice, s), "load w");
   PGM_HIP(hipMemcpyAsync(ly.b.p, b, 4 * m->dims[layer + 1], hipMemcpyDeviceToDevice, s), "load b");
   PGM_HIP(pg::mlp_to_bf16(ly.w.as<float>(), nw, ly.w_bf.as<uint16_t>(), s), "load bf16");
+  PGM_HIP(pg::mlp_transpose_bf16(ly.w_bf.as<uint16_t>(), m->dims[layer], m->dims[layer + 1], ly.w_bft.as<uint16_t>(), s),
+          "load transpose");
   return PG_OK;
 }
 
