@@ -379,6 +379,23 @@ int pg_phase_rotate(const double* uvw_in, const void* vis_in, int64_t nvis, int3
  * weight float32 [n][n], device memory.  min_weight > 0.  Enqueue only.  Errors: PG_EINVAL. */
 int pg_weight_normalise(float* img, const float* weight, int32_t n, int32_t npol, float min_weight, void* stream);
 
+/* ------------------------------------------------------------------ UV-domain mosaics
+ * Sec. 2.2, Eq. 1: every mosaic field is gridded onto one common grid about the mosaic phase
+ * centre through its own primary beam (pg_grid with the field's PG_KIND_DEGRID kernels, whose Jones
+ * field is the beam centred on the field's pointing, and PG_ACCUMULATE), and after the FFT and the
+ * taper the image is multiplied by
+ *   gamma(l, m) = [sqrt(S) / max sqrt(S)] [1 / S],  S(l, m) = sum_i B_i(l, m)^2,
+ * the primary-beam pattern normalised to 1 over the image times the weighting correction.
+ * beams: float32 [nfields][n][n] device, B_i (power beam) at the image pixels; weight_sum: float32
+ * [n][n] device, receives S; img: float32 [npol][n][n] device, multiplied in place by
+ * scale x gamma where S >= floor_frac x max S and set to 0 elsewhere (no data there; Eq. 1 would
+ * divide by a vanishing S).  scale folds in the caller's normalisation: 1/2 for the Stokes
+ * convention of this library, whose (S^-1)^H S^-1 = 2 I makes an unpolarised sky enter the common
+ * image as 2 S I.  Allocates 256 bytes of scratch per call; enqueue only.  Errors: PG_EINVAL,
+ * PG_ENOMEM, PG_EHIP. */
+int pg_mosaic_gamma(const float* beams, int32_t nfields, int32_t n, double floor_frac, double scale, float* weight_sum,
+                    float* img, int32_t npol, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

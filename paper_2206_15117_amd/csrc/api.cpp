@@ -578,6 +578,28 @@ int pg_weight_normalise(float* img, const float* weight, int32_t n, int32_t npol
   return PG_OK;
 }
 
+int pg_mosaic_gamma(const float* beams, int32_t nfields, int32_t n, double floor_frac, double scale, float* weight_sum,
+                    float* img, int32_t npol, void* stream) {
+  g_error.clear();
+  if (!beams || !weight_sum || !img) return fail(PG_EINVAL, "beams, weight_sum and img must be non-NULL");
+  if (nfields < 1 || nfields > 65536) return fail(PG_EINVAL, "nfields must be in [1, 65536]");
+  if (n < 1 || n > 65536) return fail(PG_EINVAL, "n must be in [1, 65536]");
+  if (static_cast<int64_t>(nfields) * n * n > (int64_t(1) << 40)) return fail(PG_EINVAL, "beam cube too large");
+  if (npol < 1 || npol > 4) return fail(PG_EINVAL, "npol must be in [1, 4]");
+  if (!(floor_frac >= 0.0 && floor_frac <= 1.0)) return fail(PG_EINVAL, "floor_frac must be in [0, 1]");
+  if (!is_finite(scale)) return fail(PG_EINVAL, "scale must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    DevBuf scratch;
+    if (!scratch.alloc(256, s)) return fail(PG_ENOMEM, "device allocation failed in mosaic_gamma");
+    PG_HIP(launch_mosaic_gamma(beams, nfields, n, floor_frac, scale, weight_sum, img, npol, scratch.as<unsigned>(), s),
+           "mosaic gamma");
+  } catch (...) {
+    return fail(PG_ENOMEM, "exception in mosaic_gamma");
+  }
+  return PG_OK;
+}
+
 static int check_hogbom(const float* residual, const float* psf, const int32_t* comp_pos, const float* comp_val,
                  const int32_t* n_comp, int32_t n, int32_t npol, float gain, float threshold, int32_t max_iter) {
   if (!residual || !psf || !comp_pos || !comp_val || !n_comp)

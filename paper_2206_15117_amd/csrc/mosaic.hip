@@ -135,6 +135,49 @@ __global__ __launch_bounds__(256) void phase_rotate_kernel(const double* uvw_in,
 
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 65536)); }
 
+// UV-domain mosaic correction (Sec. 2.2, Eq. 1).  Pass 1: S = sum_i B_i^2 per pixel (written out as
+// the mosaic weight map) and its maximum (float bits of a non-negative value order like unsigned
+// integers, so one atomicMax per workgroup).  Pass 2: img *= scale sqrt(S / S_max) / S where S
+// clears floor * S_max, else 0.  HBM-bound: (nfields + 1) x 4 B, then (npol x 8 + 4) B per pixel.
+__global__ __launch_bounds__(256) void beam_sumsq_kernel(const float* __restrict__ beams, int nfields, int64_t npix,
+                                                         float* __restrict__ sumsq, unsigned* __restrict__ max_bits) {
+  float best = 0.0f;
+  for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < npix;
+       p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float s = 0.0f;
+    for (int f = 0; f < nfields; ++f) {
+      const float b = beams[f * npix + p];
+      s = fmaf(b, b, s);
+    }
+    sumsq[p] = s;
+    best = fmaxf(best, s);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) best = fmaxf(best, __shfl_xor(best, o, 64));
+  __shared__ float wb[4];
+  if ((threadIdx.x & 63) == 0) wb[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float b = fmaxf(fmaxf(wb[0], wb[1]), fmaxf(wb[2], wb[3]));
+    atomicMax(max_bits, __float_as_uint(b));
+  }
+}
+
+__global__ __launch_bounds__(256) void mosaic_gamma_kernel(const float* __restrict__ sumsq,
+                                                           const unsigned* __restrict__ max_bits, float floor_frac,
+                                                           float scale, int npol, int64_t npix, float* __restrict__ img) {
+  const float smax = __uint_as_float(*max_bits);
+  const float inv_root_max = smax > 0.0f ? 1.0f / sqrtf(smax) : 0.0f;
+  for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < npix;
+       p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float s = sumsq[p];
+    const float g = (s > 0.0f && s >= floor_frac * smax) ? scale * (sqrtf(s) * inv_root_max) / s : 0.0f;
+    for (int q = 0; q < npol; ++q) img[q * npix + p] *= g;
+  }
+}
+
+__global__ void zero_u32_kernel(unsigned* p) { *p = 0u; }
+
 }  // namespace
 
 hipError_t launch_reproject(const float* src, const float* src_w, const pg_sky_frame& sf, float* dst, float* dst_w,
@@ -159,6 +202,17 @@ hipError_t launch_phase_rotate(const double* uvw_in, const void* vis_in, int64_t
   hipLaunchKernelGGL(phase_rotate_kernel, dim3(blocks_for(nvis)), dim3(256), 0, s, uvw_in,
                      static_cast<const float2*>(vis_in), nvis, npol, rotation(to, from), uvw_out,
                      static_cast<float2*>(vis_out));
+  return hipGetLastError();
+}
+
+hipError_t launch_mosaic_gamma(const float* beams, int nfields, int n, double floor_frac, double scale,
+                               float* weight_sum, float* img, int npol, unsigned* max_bits, hipStream_t s) {
+  const int64_t npix = static_cast<int64_t>(n) * n;
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((npix + 255) / 256, 8192));
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, max_bits);
+  hipLaunchKernelGGL(beam_sumsq_kernel, dim3(blocks), dim3(256), 0, s, beams, nfields, npix, weight_sum, max_bits);
+  hipLaunchKernelGGL(mosaic_gamma_kernel, dim3(blocks), dim3(256), 0, s, weight_sum, max_bits,
+                     static_cast<float>(floor_frac), static_cast<float>(scale), npol, npix, img);
   return hipGetLastError();
 }
 

@@ -9,4 +9,6 @@ hipError_t launch_weight_normalise(float* img, const float* weight, int n, int n
 hipError_t launch_phase_rotate(const double* uvw_in, const void* vis_in, int64_t nvis, int npol, double ra_from,
                                double dec_from, double ra_to, double dec_to, double* uvw_out, void* vis_out,
                                hipStream_t s);
+hipError_t launch_mosaic_gamma(const float* beams, int nfields, int n, double floor_frac, double scale,
+                               float* weight_sum, float* img, int npol, unsigned* max_bits, hipStream_t s);
 }  // namespace pg

@@ -88,6 +88,8 @@ EXPORTS = {
                           c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pg_hogbom_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, ctypes.c_float,
                                   c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pg_mosaic_gamma": (c_int, [c_void_p, c_int32, c_int32, c_double, c_double, c_void_p, c_void_p, c_int32,
+                                c_void_p]),
     "pg_kernels_export": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "pg_kernels_import": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "pg_mlp_create": (c_int, [c_int32, c_int32, c_int32, c_int64, c_int32, ctypes.c_uint64, c_void_p,
@@ -497,6 +499,25 @@ def hogbom(residual, psf, mask=None, gain: float = 0.1, threshold: float = 0.0, 
               _stream(stream)))
     m = int(cnt.item())
     return pos[:m], val[:m]
+
+
+def mosaic_gamma(beams, img, floor: float = 1e-3, scale: float = 0.5, weight_sum=None, stream=None):
+    """UV-domain mosaic correction (pg_mosaic_gamma, Eq. 1): img float32 [npol, n, n] is multiplied in
+    place by scale x gamma from the fields' power beams float32 [nfields, n, n]; returns S = sum B^2."""
+    import torch
+
+    if beams.dtype != torch.float32 or beams.dim() != 3 or not beams.is_contiguous() or beams.shape[1] != beams.shape[2]:
+        raise ValueError("beams must be contiguous float32 [nfields, n, n]")
+    n = beams.shape[-1]
+    if img.dtype != torch.float32 or img.dim() != 3 or tuple(img.shape[1:]) != (n, n) or not img.is_contiguous():
+        raise ValueError("img must be contiguous float32 [npol, n, n] on the beams' grid")
+    if weight_sum is None:
+        weight_sum = torch.empty((n, n), dtype=torch.float32, device=beams.device)
+    elif weight_sum.dtype != torch.float32 or tuple(weight_sum.shape) != (n, n) or not weight_sum.is_contiguous():
+        raise ValueError("weight_sum must be contiguous float32 [n, n]")
+    _check(lib().pg_mosaic_gamma(_ptr(beams), int(beams.shape[0]), int(n), float(floor), float(scale),
+                                 _ptr(weight_sum), _ptr(img), int(img.shape[0]), _stream(stream)))
+    return weight_sum
 
 
 class Batch:
