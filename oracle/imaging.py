@@ -30,13 +30,14 @@ def grid_from_model(geom, model: np.ndarray) -> np.ndarray:
     return np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(m, axes=(-2, -1)), axes=(-2, -1)), axes=(-2, -1)) * n2
 
 
-def dft_predict(uvw, src_l, src_m, src_stokes, beam=None, convention: str = "iau") -> np.ndarray:
+def dft_predict(uvw, src_l, src_m, src_stokes, beam=None, convention: str = "iau", beam_b=None) -> np.ndarray:
     """Direct evaluation of Eq. 2 for point sources.
 
     Stokes-I only (src_stokes [nsrc][1], no beam): V = sum_j I_j e^{+2 pi i (u l + v m + w (n-1))}.
     Full polarisation (src_stokes [nsrc][4] = I, Q, U, V): the correlations
     XX, XY, YX, YY are V = sum_j S^-1 M^S(l_j, m_j) I_j e^{...}, with M from the beam's
-    Jones matrix at the source (identity when beam is None).
+    Jones matrix at the source (identity when beam is None); with beam_b, every row is a
+    baseline between an antenna of `beam` and one of `beam_b`: M = J_a (x) conj(J_b).
     """
     src_l = np.asarray(src_l, dtype=np.float64)
     src_m = np.asarray(src_m, dtype=np.float64)
@@ -49,7 +50,7 @@ def dft_predict(uvw, src_l, src_m, src_stokes, beam=None, convention: str = "iau
     if beam is None:
         m = np.broadcast_to(np.eye(4, dtype=np.complex128), (src_l.shape[0], 4, 4))
     else:
-        m = mueller_from_jones(beam.jones(src_l, src_m))
+        m = mueller_from_jones(beam.jones(src_l, src_m), None if beam_b is None else beam_b.jones(src_l, src_m))
     corr = np.einsum("jcq,jq->jc", np.linalg.inv(s)[None] @ stokes_mueller(m, s), stokes)
     return phase @ corr
 

@@ -4,7 +4,9 @@ Readings of the paper (Sec. 3.2-3.3):
 
   * Mueller from Jones (Sec. 3.2, the Kronecker product under Eq. 2): the
     paper writes J_i (x) J_j; the conjugate J_i (x) conj(J_j) is taken, the
-    textbook measurement equation, without which M^S is not real.
+    textbook measurement equation, without which M^S is not real.  Antennas
+    are identical unless a second Jones field is given (a baseline between two
+    antenna types); M^S is then complex in general.
   * Correlation order XX, XY, YX, YY (Eq. 3).
   * Stokes substitution (Eq. 4): the paper prints U with a factor i; the
     reading is U = (XY + YX)/2 (IAU), under which M^S is real.  The
@@ -30,10 +32,11 @@ def stokes_matrix(convention: str = "iau") -> np.ndarray:
                      [0, -0.5j, 0.5j, 0]], dtype=np.complex128)
 
 
-def mueller_from_jones(j: np.ndarray) -> np.ndarray:
-    """M = J (x) conj(J) per sample; j is [..., 2, 2], the result [..., 4, 4]."""
+def mueller_from_jones(j: np.ndarray, j_b: np.ndarray = None) -> np.ndarray:
+    """M = J (x) conj(J) per sample; j is [..., 2, 2], the result [..., 4, 4].  With j_b, the
+    Mueller matrix of a baseline between two different antennas, J_a (x) conj(J_b) (Sec. 3.2)."""
     j = np.asarray(j, dtype=np.complex128)
-    jc = np.conj(j)
+    jc = np.conj(j if j_b is None else np.asarray(j_b, dtype=np.complex128))
     out = np.empty(j.shape[:-2] + (4, 4), dtype=np.complex128)
     for a in range(2):
         for b in range(2):
@@ -65,19 +68,26 @@ def jones_field_to_pixels(jones: np.ndarray) -> np.ndarray:
     return np.moveaxis(np.asarray(jones, dtype=np.complex128), (0, 1), (2, 3))
 
 
-def phi_grid(jones, eps: float, convention: str = "iau") -> np.ndarray:
-    """Gridding screens Phi = (M'^S)^-1 S, shape [Q=4][C=4][rows][cols] (Sec. 3.2-3.3)."""
+def _ms_field(jones, jones_b, s):
+    jb = None if jones_b is None else jones_field_to_pixels(jones_b)
+    return stokes_mueller(mueller_from_jones(jones_field_to_pixels(jones), jb), s)
+
+
+def phi_grid(jones, eps: float, convention: str = "iau", jones_b=None) -> np.ndarray:
+    """Gridding screens Phi = (M'^S)^-1 S, shape [Q=4][C=4][rows][cols] (Sec. 3.2-3.3); with jones_b,
+    those of the baseline between antennas with Jones fields jones and jones_b."""
     s = stokes_matrix(convention)
-    ms = stokes_mueller(mueller_from_jones(jones_field_to_pixels(jones)), s)
+    ms = _ms_field(jones, jones_b, s)
     minv = np.linalg.inv(regularise_diagonal(ms, eps))
     phi = minv @ s
     return np.moveaxis(phi, (-2, -1), (0, 1))
 
 
-def phi_degrid(jones, convention: str = "iau") -> np.ndarray:
-    """Degridding screens Phi = (S^-1 M^S)^H, shape [Q=4][C=4][rows][cols] (Sec. 3.2, Eq. 2)."""
+def phi_degrid(jones, convention: str = "iau", jones_b=None) -> np.ndarray:
+    """Degridding screens Phi = (S^-1 M^S)^H, shape [Q=4][C=4][rows][cols] (Sec. 3.2, Eq. 2); with
+    jones_b, those of the baseline between antennas with Jones fields jones and jones_b."""
     s = stokes_matrix(convention)
-    ms = stokes_mueller(mueller_from_jones(jones_field_to_pixels(jones)), s)
+    ms = _ms_field(jones, jones_b, s)
     a = np.linalg.inv(s) @ ms
     phi = np.conj(np.swapaxes(a, -1, -2))
     return np.moveaxis(phi, (-2, -1), (0, 1))
