@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-scale", action="store_true", help="skip the 20M-row major-cycle section")
     ap.add_argument("--no-clean", action="store_true", help="skip the Cotton-Schwab clean section")
     ap.add_argument("--no-mosaic", action="store_true", help="skip the 7-field mosaic section")
+    ap.add_argument("--no-uv-mosaic", action="store_true", help="skip the 7-field UV-domain mosaic section")
     ap.add_argument("--network-only", action="store_true",
                     help="time only the kernel network's products (forward at batch 256 and 2048, one training "
                          "step) on the 24 -> 3 x 256 -> 294912 shape and print that section as the JSON line")
@@ -229,6 +230,10 @@ def main():
         torch.cuda.empty_cache()
         out["mosaic"] = bench_mosaic(2, 1)
         log(f"mosaic step timed: {out['mosaic']['ms_per_step']:.1f} ms")
+    if not args.no_uv_mosaic:
+        torch.cuda.empty_cache()
+        out["uv_mosaic"] = bench_uv_mosaic(2, 1)
+        log(f"uv mosaic step timed: {out['uv_mosaic']['ms_per_step']:.1f} ms")
     if not args.no_surrogate:
         torch.cuda.empty_cache()
         out["network"] = bench_network()
@@ -572,6 +577,102 @@ def bench_mosaic(steps, warmup):
             "phase_rotate_roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                                       "achieved": w.nvis * 112 / (ms["phase_rotate"] * 1e-3) / 1e9,
                                       "frac": w.nvis * 112 / (ms["phase_rotate"] * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
+def bench_uv_mosaic(steps, warmup):
+    """The same 7 pointings as a UV-domain mosaic (Sec. 2.2, Eq. 1): config 5's 20M rows, stored about
+    the mosaic centre, gridded field by field onto ONE common 10240^2 x 4 grid through each field's
+    own beam kernels (the 1-degree Gaussian beam with 1 % leakage centred on the field's pointing),
+    then one FFT, the taper and the gamma correction; the prediction goes back through the same
+    kernels (taper -> inverse FFT -> degrid per field).  Supports follow the support rule for the
+    mosaic's field of view.  Input visibilities: a 1000-component model predicted through the fields'
+    kernels, each field divided by its own row count (natural weights within a field)."""
+    import torch
+
+    import synth
+    from paper_2206_15117_amd import autotune
+    from paper_2206_15117_amd import mosaic as mos
+    from paper_2206_15117_amd import polgrid as pg
+
+    w, centres, mf = synth.config5_mosaic()
+    nm, cell, ra0, dec0 = mf
+    g5 = w.geom
+    base = synth.Geometry(n=nm, cell=cell, os=g5.os, w_planes=g5.w_planes,
+                          support=synth.support_rule(g5.w_planes, nm * cell), aa_support=g5.aa_support, mk=g5.mk)
+    launch = autotune.apply(base, 4, pg.STORE_F32)
+    g = launch.geom
+    nf = len(centres)
+    t0 = time.perf_counter()
+    ks, beams = [], []
+    pix = torch.empty((nf, nm, nm), dtype=torch.float32, device="cuda")
+    x = (torch.arange(nm, device="cuda", dtype=torch.float64) - nm // 2) * cell
+    for f, (ra, dec) in enumerate(centres):
+        # pointing offset in the mosaic frame (orthographic projection about the mosaic centre)
+        l0 = math.cos(dec) * math.sin(ra - ra0)
+        m0 = math.sin(dec) * math.cos(dec0) - math.cos(dec) * math.sin(dec0) * math.cos(ra - ra0)
+        b = synth.OffsetBeam(w.beam, l0, m0)
+        ks.append(pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=synth.jones_on_lattice(b, g.mk, g.fov)))
+        # power beam E^2 of the 1-degree Gaussian at the pixels (input instrument model)
+        pix[f] = torch.exp(-4.0 * math.log(2.0) * ((x[None, :] - l0) ** 2 + (x[:, None] - m0) ** 2)
+                           / w.beam.theta ** 2).float()
+    del x
+    torch.cuda.synchronize()
+    t_kernels = time.perf_counter() - t0
+    bounds = np.linspace(0, w.nvis, nf + 1).astype(np.int64)
+    uvws = [torch.from_numpy(np.ascontiguousarray(w.uvw[a:b])).cuda() for a, b in zip(bounds[:-1], bounds[1:])]
+    plans = [autotune.plan(k, u, launch) for k, u in zip(ks, uvws)]
+    model = torch.zeros((4, nm, nm), dtype=torch.float32, device="cuda")
+    jj = np.clip(np.round(w.src_l / cell).astype(int) + nm // 2, 0, nm - 1)
+    ii = np.clip(np.round(w.src_m / cell).astype(int) + nm // 2, 0, nm - 1)
+    idx = torch.from_numpy((ii * nm + jj).astype(np.int64)).cuda()
+    for q in range(4):
+        model[q].view(-1).index_add_(0, idx, torch.from_numpy(w.src_iquv[:, q].astype(np.float32)).cuda())
+    vis = [pg.predict(p, k, model) / float(max(p.n_kept, 1)) for p, k in zip(plans, ks)]
+    log("uv mosaic inputs predicted")
+    grid_buf = torch.empty((4, nm, nm), dtype=torch.complex64, device="cuda")
+    img = torch.empty((4, nm, nm), dtype=torch.float32, device="cuda")
+    wmap = torch.empty((nm, nm), dtype=torch.float32, device="cuda")
+    vis_out = [torch.empty_like(v) for v in vis]
+    ev = {k: [] for k in ("plan", "grid", "fft_taper_gamma", "predict")}
+
+    def ev_now():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def step(rec):
+        e0 = ev_now()
+        ps = [autotune.plan(k, u, launch) for k, u in zip(ks, uvws)]
+        e1 = ev_now()
+        for f in range(nf):
+            pg.grid(ps[f], ks[f], vis[f], out=grid_buf, accumulate=f > 0, fftshift=True)
+        e2 = ev_now()
+        pg.taper(ks[0], torch.fft.fft2(grid_buf), img, pg.TAPER_IMAGE, 1.0)
+        pg.mosaic_gamma(pix, img, floor=1e-3, scale=0.5, weight_sum=wmap)
+        e3 = ev_now()
+        pg.taper(ks[0], img, grid_buf, pg.TAPER_PREDICT)
+        gm = torch.fft.ifft2(grid_buf, norm="forward")
+        for f in range(nf):
+            pg.degrid(ps[f], ks[f], gm, out=vis_out[f], fftshift=True)
+        e4 = ev_now()
+        if rec:
+            for k, a, b in (("plan", e0, e1), ("grid", e1, e2), ("fft_taper_gamma", e2, e3), ("predict", e3, e4)):
+                ev[k].append((a, b))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = {k: float(sum(a.elapsed_time(b) for a, b in v) / steps) for k, v in ev.items()}
+    return {"workload": f"7-field UV-domain mosaic of the major cycle: {nf} pointings (hexagon at 0.5 deg) gridded "
+                        f"through their own beam kernels onto one {nm}x{nm}x4 grid about the mosaic centre, "
+                        f"{w.nvis} rows, {g.nplanes} w-planes, supports {int(g.support.min())}-{int(g.support.max())}",
+            "rows": w.nvis, "fields": nf, "value": w.nvis / wall, "unit": "vis/s", "ms_per_step": 1e3 * wall,
+            "breakdown_ms": ms, "make_kernels_s": t_kernels}
 
 
 def bench_network(batches=(256, 2048), reps=10):
