@@ -103,6 +103,10 @@ typedef struct pg_kernel_spec {
   double eps_null;           /* Eq. 6 mask fraction epsilon (0.2 typical); used by PG_KIND_GRID */
   int32_t stokes_convention; /* PG_STOKES_IAU or PG_STOKES_PAPER */
   int32_t storage;           /* PG_STORE_F32 or PG_STORE_F16 */
+  const double* jones_b;     /* host complex128 [2][2][mk][mk] or NULL: the second antenna's Jones field
+                                of a baseline between two antenna types; the Mueller matrix is then
+                                J_a (x) conj(J_b) with J_a from `jones` (Sec. 3.2), so kernels are
+                                unique to the baseline class.  NULL: identical antennas */
 } pg_kernel_spec;
 
 typedef struct pg_kernels pg_kernels;

@@ -82,13 +82,15 @@ int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** ou
   if (!(spec->eps_null >= 0.0) || !is_finite(spec->eps_null)) return fail(PG_EINVAL, "eps_null must be finite and >= 0");
   int rc = check_geometry(spec->g, spec->npol);
   if (rc != PG_OK) return rc;
-  if (spec->npol == 1 && spec->jones) return fail(PG_EUNSUPPORTED, "npol = 1 (Stokes I only) takes no Jones field");
+  if (spec->npol == 1 && (spec->jones || spec->jones_b))
+    return fail(PG_EUNSUPPORTED, "npol = 1 (Stokes I only) takes no Jones field");
 
   const pg_geometry& g = spec->g;
   const int mk = g.mk, np = spec->npol, nqc = np * np;
   std::vector<double> phi;
   std::string err;
-  if (generate && !build_screens(np, spec->kind, spec->jones, mk, spec->eps_null, spec->stokes_convention, phi, err))
+  if (generate &&
+      !build_screens(np, spec->kind, spec->jones, spec->jones_b, mk, spec->eps_null, spec->stokes_convention, phi, err))
     return fail(PG_EINVAL, err);
 
   auto* k = new (std::nothrow) pg_kernels();

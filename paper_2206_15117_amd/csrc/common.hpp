@@ -210,7 +210,7 @@ hipError_t launch_batch_degrid(const pg_batch* b, int flags, hipStream_t s);
 // Host numerics (pswf.cpp, mueller.cpp)
 std::vector<double> pswf0(double c, const std::vector<double>& x);
 // Screens Phi[q][c][mk][mk] (complex, interleaved) for the given kind.
-bool build_screens(int npol, int kind, const double* jones, int mk, double eps, int convention,
+bool build_screens(int npol, int kind, const double* jones, const double* jones_b, int mk, double eps, int convention,
                    std::vector<double>& phi, std::string& err);
 
 }  // namespace pg

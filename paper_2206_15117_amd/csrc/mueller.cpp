@@ -1,7 +1,7 @@
 // Image-domain screens Phi_qc(l, m) of the Mueller kernels, host float64.
 //
-// Sec. 3.2: Mueller matrices from identical-antenna Jones matrices,
-// M = J (x) conj(J) in correlation order XX, XY, YX, YY (Eq. 3); Stokes form
+// Sec. 3.2: Mueller matrices from the Jones matrices of a baseline's two antennas,
+// M = J_a (x) conj(J_b) (identical antennas: J_b = J_a) in correlation order XX, XY, YX, YY (Eq. 3); Stokes form
 // M^S = S M S^-1 with S from Eq. 4 (U = (XY + YX)/2 by default, the printed
 // U = i (XY + YX)/2 on request).  Gridding screens are (M'^S)^-1 S, where M' has
 // its diagonal regularised by Eq. 6 (Sec. 3.3); degridding screens are
@@ -101,11 +101,11 @@ M4 stokes(int convention) {
 
 }  // namespace
 
-bool build_screens(int npol, int kind, const double* jones, int mk, double eps, int convention,
+bool build_screens(int npol, int kind, const double* jones, const double* jones_b, int mk, double eps, int convention,
                    std::vector<double>& phi, std::string& err) {
   const size_t npix = static_cast<size_t>(mk) * mk;
   if (npol == 1) {
-    if (jones) {
+    if (jones || jones_b) {
       err = "npol = 1 (Stokes I only) takes no Jones field";
       return false;
     }
@@ -123,21 +123,19 @@ bool build_screens(int npol, int kind, const double* jones, int mk, double eps, 
   std::vector<M4> ms(npix);
   parallel_for(npix, [&](size_t px0, size_t px1) {
   for (size_t px = px0; px < px1; ++px) {
-    cd j[2][2];
+    // the baseline's two antennas: J_a from `jones`, J_b from `jones_b` (identical antennas when NULL)
+    cd ja[2][2], jb[2][2];
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
-        if (jones) {
-          const double* e = jones + 2 * ((static_cast<size_t>(a) * 2 + b) * npix + px);
-          j[a][b] = cd(e[0], e[1]);
-        } else {
-          j[a][b] = (a == b) ? 1.0 : 0.0;
-        }
+        const size_t o = 2 * ((static_cast<size_t>(a) * 2 + b) * npix + px);
+        ja[a][b] = jones ? cd(jones[o], jones[o + 1]) : cd((a == b) ? 1.0 : 0.0);
+        jb[a][b] = jones_b ? cd(jones_b[o], jones_b[o + 1]) : ja[a][b];
       }
     M4 m;
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 2; ++c)
-          for (int d = 0; d < 2; ++d) m.a[2 * a + b][2 * c + d] = j[a][c] * std::conj(j[b][d]);
+          for (int d = 0; d < 2; ++d) m.a[2 * a + b][2 * c + d] = ja[a][c] * std::conj(jb[b][d]);
     ms[px] = mul(mul(s, m), sinv);
   }
   });

@@ -31,7 +31,8 @@ class PgGeometry(ctypes.Structure):
 
 class PgKernelSpec(ctypes.Structure):
     _fields_ = [("g", PgGeometry), ("npol", c_int32), ("kind", c_int32), ("jones", POINTER(c_double)),
-                ("eps_null", c_double), ("stokes_convention", c_int32), ("storage", c_int32)]
+                ("eps_null", c_double), ("stokes_convention", c_int32), ("storage", c_int32),
+                ("jones_b", POINTER(c_double))]
 
 
 class PgKernelsDesc(ctypes.Structure):
@@ -252,16 +253,21 @@ class Kernels:
 
 
 def make_kernels(geom, npol: int, kind: int = KIND_GRID, jones=None, eps_null: float = 0.2,
-                 storage: int = STORE_F32, convention: int = STOKES_IAU, stream=None) -> Kernels:
+                 storage: int = STORE_F32, convention: int = STOKES_IAU, stream=None, jones_b=None) -> Kernels:
+    """Kernel set (pg_make_kernels).  jones: the antennas' Jones field [2][2][mk][mk]; jones_b: the
+    second antenna's of a baseline between two antenna types (Mueller J_a (x) conj(J_b))."""
     g, keep = _geometry_struct(geom)
-    jp = None
-    if jones is not None:
-        jarr = np.ascontiguousarray(jones, dtype=np.complex128)
+    ptrs = []
+    for j in (jones, jones_b):
+        if j is None:
+            ptrs.append(None)
+            continue
+        jarr = np.ascontiguousarray(j, dtype=np.complex128)
         if jarr.shape != (2, 2, geom.mk, geom.mk):
-            raise ValueError(f"jones must be complex128 [2][2][mk][mk], got {jarr.shape}")
+            raise ValueError(f"Jones fields must be complex128 [2][2][mk][mk], got {jarr.shape}")
         keep = keep + (jarr,)
-        jp = jarr.ctypes.data_as(POINTER(c_double))
-    spec = PgKernelSpec(g, int(npol), int(kind), jp, float(eps_null), int(convention), int(storage))
+        ptrs.append(jarr.ctypes.data_as(POINTER(c_double)))
+    spec = PgKernelSpec(g, int(npol), int(kind), ptrs[0], float(eps_null), int(convention), int(storage), ptrs[1])
     h = c_void_p()
     _check(lib().pg_make_kernels(ctypes.byref(spec), _stream(stream), ctypes.byref(h)))
     return Kernels(h, geom)
@@ -270,7 +276,7 @@ def make_kernels(geom, npol: int, kind: int = KIND_GRID, jones=None, eps_null: f
 def kernels_alloc(geom, npol: int, kind: int = KIND_GRID, storage: int = STORE_F32, stream=None) -> Kernels:
     """A kernel set of this geometry whose table is zero, to be filled with Kernels.import_planes."""
     g, keep = _geometry_struct(geom)
-    spec = PgKernelSpec(g, int(npol), int(kind), None, 0.0, STOKES_IAU, int(storage))
+    spec = PgKernelSpec(g, int(npol), int(kind), None, 0.0, STOKES_IAU, int(storage), None)
     h = c_void_p()
     _check(lib().pg_kernels_alloc(ctypes.byref(spec), _stream(stream), ctypes.byref(h)))
     return Kernels(h, geom)

@@ -184,6 +184,24 @@ class OffsetBeam:
         return np.abs(self.jones(l, m)[..., 0, 0]) ** 2
 
 
+def antenna_types(theta: float, k: int, rng, pointing_sigma: float, level: float = 0.01) -> list:
+    """k antenna types: the Gaussian beam of power FWHM theta, each type with its own seeded leakage
+    pattern and a pointing error drawn N(0, pointing_sigma) per axis (radians)."""
+    out = []
+    for _ in range(k):
+        b = seeded_leakage_beam(theta, rng, level=level)
+        out.append(OffsetBeam(b, float(rng.normal(0.0, pointing_sigma)), float(rng.normal(0.0, pointing_sigma))))
+    return out
+
+
+def baseline_type_pairs(n_rows: int, n_ant: int, k: int) -> np.ndarray:
+    """Ordered antenna-type pair index (type_a k + type_b) of every row of time-major tracks
+    (row r is baseline r mod n_baselines), antenna i being of type i mod k."""
+    pairs = baseline_pairs(n_ant)
+    bl = pairs[np.arange(n_rows) % pairs.shape[0]]
+    return (bl[:, 0] % k) * k + (bl[:, 1] % k)
+
+
 def power_on_pixels(beam, n: int, cell: float) -> np.ndarray:
     """float64 [n (m, rows)][n (l, columns)] power beam at the image pixel centres."""
     x = (np.arange(n) - n // 2) * cell
