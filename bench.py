@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-clean", action="store_true", help="skip the Cotton-Schwab clean section")
     ap.add_argument("--no-mosaic", action="store_true", help="skip the 7-field mosaic section")
     ap.add_argument("--no-uv-mosaic", action="store_true", help="skip the 7-field UV-domain mosaic section")
+    ap.add_argument("--no-per-baseline", action="store_true", help="skip the per-baseline Mueller kernel section")
     ap.add_argument("--network-only", action="store_true",
                     help="time only the kernel network's products (forward at batch 256 and 2048, one training "
                          "step) on the 24 -> 3 x 256 -> 294912 shape and print that section as the JSON line")
@@ -230,6 +231,10 @@ def main():
         torch.cuda.empty_cache()
         out["mosaic"] = bench_mosaic(2, 1)
         log(f"mosaic step timed: {out['mosaic']['ms_per_step']:.1f} ms")
+    if not args.no_per_baseline:
+        torch.cuda.empty_cache()
+        out["per_baseline"] = bench_per_baseline(3, 1)
+        log(f"per-baseline step timed: {out['per_baseline']['ms_per_step']:.1f} ms")
     if not args.no_uv_mosaic:
         torch.cuda.empty_cache()
         out["uv_mosaic"] = bench_uv_mosaic(2, 1)
@@ -673,6 +678,106 @@ def bench_uv_mosaic(steps, warmup):
                         f"{w.nvis} rows, {g.nplanes} w-planes, supports {int(g.support.min())}-{int(g.support.max())}",
             "rows": w.nvis, "fields": nf, "value": w.nvis / wall, "unit": "vis/s", "ms_per_step": 1e3 * wall,
             "breakdown_ms": ms, "make_kernels_s": t_kernels}
+
+
+def bench_per_baseline(steps, warmup):
+    """Per-baseline Mueller kernels on the full-pol workload: the 36 antennas are of three types (the
+    1-degree beam with each type's own 1 % leakage and a 2-arcmin rms pointing error), so a baseline's
+    Mueller matrix J_a (x) conj(J_b) depends on its ordered type pair: nine kernel sets, rows split
+    by pair, one batched launch grids all nine onto one grid and one degrids them (with FFT and both
+    tapers between).  The sky (50 polarised sources) is predicted through each pair's own kernels;
+    the image made with the per-pair kernels is compared with the image made with the kernels of
+    the antenna-averaged beam (mean Jones field, the paper's averaging for performance)."""
+    import torch
+
+    import synth
+    from paper_2206_15117_amd import autotune
+    from paper_2206_15117_amd import polgrid as pg
+
+    k_types = 3
+    w = synth.config2()
+    launch = autotune.apply(w.geom, 4, pg.STORE_F32)
+    g = launch.geom
+    rng = np.random.default_rng(2206151171)
+    types = synth.antenna_types(1.0 * synth.DEG, k_types, rng, pointing_sigma=2.0 / 60.0 * synth.DEG)
+    jl = [synth.jones_on_lattice(t, g.mk, g.fov) for t in types]
+    pair = synth.baseline_type_pairs(w.nvis, 36, k_types)
+    t0 = time.perf_counter()
+    groups = []
+    for p in range(k_types * k_types):
+        rows = np.flatnonzero(pair == p)
+        ta, tb = p // k_types, p % k_types
+        kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jl[ta], jones_b=jl[tb], eps_null=w.eps_null)
+        kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jl[ta], jones_b=jl[tb])
+        uvw = torch.from_numpy(np.ascontiguousarray(w.uvw[rows])).cuda()
+        groups.append((kg, kd, uvw, rows.size))
+    torch.cuda.synchronize()
+    t_kernels = time.perf_counter() - t0
+    n = g.n
+    model = torch.zeros((4, n, n), dtype=torch.float32, device="cuda")
+    jj = np.clip(np.round(w.src_l / g.cell).astype(int) + n // 2, 0, n - 1)
+    ii = np.clip(np.round(w.src_m / g.cell).astype(int) + n // 2, 0, n - 1)
+    for s in range(len(jj)):
+        model[:, ii[s], jj[s]] += torch.from_numpy(w.src_iquv[s].astype(np.float32)).cuda()
+    plans = [(autotune.plan(kg, uvw, launch), autotune.plan(kd, uvw, launch)) for kg, kd, uvw, _ in groups]
+    vis = [pg.predict(pd, kd, model) for (_, pd), (_, kd, _, _) in zip(plans, groups)]
+    del model
+    grid = torch.empty((4, n, n), dtype=torch.complex64, device="cuda")
+    gmod = torch.empty_like(grid)
+    pbuf = torch.empty_like(grid)
+    img = torch.empty((4, n, n), dtype=torch.float32, device="cuda")
+    outs = [torch.empty_like(v) for v in vis]
+    bg = pg.batch([(pgr, kg, v, grid) for (pgr, _), (kg, _, _, _), v in zip(plans, groups, vis)])
+    bd = pg.batch([(pd, kd, o, gmod) for (_, pd), (_, kd, _, _), o in zip(plans, groups, outs)])
+    nkept = float(sum(pgr.n_kept for pgr, _ in plans))
+    kg0, kd0 = groups[0][0], groups[0][1]
+    ev = {k: [] for k in ("grid", "fft_taper", "degrid")}
+
+    def step(rec):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        bg.grid(fftshift=True)
+        e[1].record()
+        pg.taper(kg0, torch.fft.fft2(grid), img, pg.TAPER_IMAGE, nkept)
+        pg.taper(kd0, img, pbuf, pg.TAPER_PREDICT)
+        torch.fft.ifft2(pbuf, norm="forward", out=gmod)
+        e[2].record()
+        bd.degrid(fftshift=True)
+        e[3].record()
+        if rec:
+            for k, a, b in (("grid", 0, 1), ("fft_taper", 1, 2), ("degrid", 2, 3)):
+                ev[k].append((e[a], e[b]))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    # image with per-pair kernels (the step's last image) against the antenna-averaged beam's kernels
+    bg.grid(fftshift=True)
+    i_pair = pg.taper(kg0, torch.fft.fft2(grid), torch.empty_like(img), pg.TAPER_IMAGE, nkept)
+    mean_j = sum(jl) / len(jl)
+    kavg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=mean_j, eps_null=w.eps_null)
+    grid.zero_()
+    for (kg, _, uvw, _), v in zip(groups, vis):
+        pa = autotune.plan(kavg, uvw, launch)
+        pg.grid(pa, kavg, v, out=grid, accumulate=True, fftshift=True)
+    i_avg = pg.taper(kavg, torch.fft.fft2(grid), torch.empty_like(img), pg.TAPER_IMAGE, nkept)
+    torch.cuda.synchronize()
+    inner = slice(n // 4, 3 * n // 4)
+    peak = float(i_pair[0, inner, inner].abs().max())
+    rms = [float((i_avg[q, inner, inner] - i_pair[q, inner, inner]).pow(2).mean().sqrt()) / peak for q in range(4)]
+    return {"workload": f"full-pol 2048^2 x 4 workload with three antenna types (own leakage, 2 arcmin rms pointing "
+                        f"error): nine ordered type-pair kernel sets, {w.nvis} rows split by pair, one batched "
+                        f"launch each way",
+            "kernel_sets": k_types * k_types, "rows": w.nvis, "value": w.nvis / wall, "unit": "vis/s",
+            "ms_per_step": 1e3 * wall, "breakdown_ms": ms, "make_kernels_s": t_kernels,
+            "image_rms_averaged_vs_per_pair_kernels": {"I": rms[0], "Q": rms[1], "U": rms[2], "V": rms[3]},
+            "note": "rms over the inner half of the image / Stokes-I peak of the per-pair image"}
 
 
 def bench_network(batches=(256, 2048), reps=10):
