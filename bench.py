@@ -215,6 +215,10 @@ def main():
                      "l2_peak_TBps_derived": L2_PEAK_TBS},
         "source_hash": src,
     }
+    out["deterministic_grid"] = bench_deterministic(p, kg, vis, grid_buf, ms["grid"])
+    log(f"reproducible grid timed: {out['deterministic_grid']['ms']:.2f} ms")
+    out["c1"] = bench_c1()
+    log(f"c1 step timed: {out['c1']['ms_per_step']:.2f} ms")
     if not args.no_clean:
         out["clean"] = bench_clean(w, g, p, kg, kd, vis)
         log(f"clean timed: {out['clean']['ms_total']:.1f} ms")
@@ -247,6 +251,34 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def bench_deterministic(p, kg, vis, grid_buf, ms_atomic, reps=3):
+    """The c2 grid in the reproducible mode (fixed-point accumulation): time per call, whether two
+    calls give the same bits, and its distance from the float-atomic grid."""
+    import torch
+
+    from paper_2206_15117_amd import polgrid as pg
+
+    pg.grid(p, kg, vis, out=grid_buf, fftshift=True)
+    ref = grid_buf.clone()
+    a = pg.grid(p, kg, vis, fftshift=True, deterministic=True)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pg.grid(p, kg, vis, out=grid_buf, fftshift=True, deterministic=True)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    same = bool(torch.equal(torch.view_as_real(a), torch.view_as_real(grid_buf)))
+    diff = float((torch.view_as_real(a) - torch.view_as_real(ref)).norm() / torch.view_as_real(ref).norm())
+    del a, ref
+    return {"ms": float(np.mean(times)), "ms_float_atomic": ms_atomic, "same_bits_twice": same,
+            "rel_l2_vs_float_atomic": diff,
+            "note": "per call, including the bound passes, the per-call scratch allocation (caching allocator) "
+                    "and the fixed-point conversion"}
 
 
 def bench_batched(steps, warmup):
@@ -680,6 +712,62 @@ def bench_uv_mosaic(steps, warmup):
             "breakdown_ms": ms, "make_kernels_s": t_kernels}
 
 
+def bench_c1(steps=50, warmup=5):
+    """The small Stokes-I configuration (256^2, 8 w-planes, support 7, os 4, 20k rows in a 100-
+    wavelength disc): the same step as the headline (plan -> grid -> FFT -> taper -> taper ->
+    inverse FFT -> degrid).  Its work is microseconds per stage, so the step measures launch and
+    synchronisation latency, not a roofline."""
+    import torch
+
+    import synth
+    from paper_2206_15117_amd import polgrid as pg
+
+    w = synth.config1()
+    g = w.geom
+    kg = pg.make_kernels(g, 1, pg.KIND_GRID)
+    kd = pg.make_kernels(g, 1, pg.KIND_DEGRID)
+    uvw = torch.from_numpy(w.uvw).cuda()
+    vis = torch.from_numpy(synth.random_vis(w.nvis, 1, np.random.default_rng(5))).cuda()
+    n = g.n
+    grid = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    img = torch.empty((1, n, n), dtype=torch.float32, device="cuda")
+    pbuf = torch.empty_like(grid)
+    out = torch.empty_like(vis)
+    ev = {k: [] for k in ("plan", "grid", "fft_taper", "degrid")}
+
+    def step(rec):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record()
+        p = pg.plan(kg, uvw, max_chunk=256)
+        e[1].record()
+        pg.grid(p, kg, vis, out=grid, fftshift=True)
+        e[2].record()
+        pg.taper(kg, torch.fft.fft2(grid), img, pg.TAPER_IMAGE, float(p.n_kept))
+        pg.taper(kd, img, pbuf, pg.TAPER_PREDICT)
+        gm = torch.fft.ifft2(pbuf, norm="forward")
+        e[3].record()
+        pg.degrid(p, kd, gm, out=out, fftshift=True)
+        e[4].record()
+        if rec:
+            for k, a, b in (("plan", 0, 1), ("grid", 1, 2), ("fft_taper", 2, 3), ("degrid", 3, 4)):
+                ev[k].append((e[a], e[b]))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    return {"workload": "Stokes-I 256x256, 8 w-planes (|w| <= 200), PSWF support 7, os 4, no A-term, 20000 rows",
+            "rows": w.nvis, "value": w.nvis / wall, "unit": "vis/s (single-pol)", "ms_per_step": 1e3 * wall,
+            "breakdown_ms": ms, "bound": "launch",
+            "note": "launch-bound: each stage is a few microseconds of work; the plan synchronises the stream "
+                    "once to return its drop count"}
+
+
 def bench_per_baseline(steps, warmup):
     """Per-baseline Mueller kernels on the full-pol workload: the 36 antennas are of three types (the
     1-degree beam with each type's own 1 % leakage and a 2-arcmin rms pointing error), so a baseline's
@@ -922,35 +1010,95 @@ def bench_surrogate(n_kernels):
             "note": "image errors: rms over the inner half of the field / Stokes-I peak of the FFT-kernel image"}
 
 
-def cpu_baseline(w, nsample):
-    """The FP64 oracle's grid + degrid on a seeded sample of the same visibilities, one core."""
+_CPU = {}
+
+
+def _oracle_grid_part(job):
+    """One pool worker: grid its slice of the sample into its own slot of the shared partial grids."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import gridding
+
+    lo, hi, slot = job
+    with threadpool_limits(limits=1):
+        _CPU["partials"][slot] = gridding.grid(_CPU["geom"], _CPU["tabs"], _CPU["uvw"][lo:hi], _CPU["vis"][lo:hi])
+    return slot
+
+
+def _oracle_degrid_part(job):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import gridding
+
+    lo, hi = job
+    with threadpool_limits(limits=1):
+        return lo, gridding.degrid(_CPU["geom"], _CPU["tabs"], _CPU["uvw"][lo:hi], _CPU["grid"])
+
+
+def cpu_baseline(w, nsample, nsample_one=120_000):
+    """The FP64 oracle's grid + degrid on a seeded sample of the same visibilities: on every host
+    core the process may use (a fork pool, one BLAS thread per worker, private partial grids in
+    shared memory summed by the parent, then the rows degridded in parallel from the sum), and on
+    one core for a sub-sample."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+
     import synth
     from oracle import gridding, kernels, mueller
+    from oracle.geometry import nearest_plane
 
     rng = np.random.default_rng(11)
     idx = np.sort(rng.choice(w.nvis, nsample, replace=False))
     uvw = w.uvw[idx]
-    from oracle.geometry import nearest_plane
-
     planes = sorted(set(nearest_plane(uvw[:, 2], w.geom.w_planes).tolist()))
     jones = synth.jones_on_lattice(w.beam, w.geom.mk, w.geom.fov)
     phi = mueller.phi_grid(jones, w.eps_null)
     tabs = [None] * w.geom.nplanes
     for i, pl in enumerate(planes):
         tabs[pl] = kernels.make_tables(w.geom, phi, planes=[pl])[pl]
-        log(f"oracle table {i + 1}/{len(planes)} built")
+        if (i + 1) % 8 == 0 or i + 1 == len(planes):
+            log(f"oracle table {i + 1}/{len(planes)} built")
     vis = synth.random_vis(nsample, 4, rng)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    n = w.geom.n
+    shm = shared_memory.SharedMemory(create=True, size=cores * 4 * n * n * 16)
+    try:
+        _CPU.update(geom=w.geom, tabs=tabs, uvw=uvw, vis=vis,
+                    partials=np.ndarray((cores, 4, n, n), dtype=np.complex128, buffer=shm.buf))
+        bounds = np.linspace(0, nsample, cores + 1).astype(np.int64)
+        ctx = mp.get_context("fork")
+        t0 = time.perf_counter()
+        with ctx.Pool(cores) as pool:
+            pool.map(_oracle_grid_part, [(int(bounds[i]), int(bounds[i + 1]), i) for i in range(cores)])
+        _CPU["grid"] = _CPU["partials"].sum(axis=0)
+        with ctx.Pool(cores) as pool:
+            parts = pool.map(_oracle_degrid_part, [(int(bounds[i]), int(bounds[i + 1])) for i in range(cores)])
+        dt_all = time.perf_counter() - t0
+        log(f"oracle grid + degrid on {cores} cores: {dt_all:.1f} s")
+    finally:
+        _CPU.clear()
+        shm.close()
+        shm.unlink()
+    del parts
     from threadpoolctl import threadpool_limits
 
+    m = min(nsample_one, nsample)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        g = gridding.grid(w.geom, tabs, uvw, vis)
-        log("oracle grid done")
-        gridding.degrid(w.geom, tabs, uvw, g)
-        dt = time.perf_counter() - t0
-    return {"value": nsample / dt, "unit": "vis/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsample} seeded rows of the 2.3M (grid + degrid, FP64 numpy, one process); "
-                      f"kernel tables built beforehand and not timed", "seconds": dt}
+        g1 = gridding.grid(w.geom, tabs, uvw[:m], vis[:m])
+        gridding.degrid(w.geom, tabs, uvw[:m], g1)
+        dt_one = time.perf_counter() - t0
+    log(f"oracle grid + degrid on one core: {dt_one:.1f} s for {m} rows")
+    return {"value": nsample / dt_all, "unit": "vis/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nsample} seeded rows of the 2.3M (grid + degrid, FP64 numpy; {cores} fork workers with "
+                      f"one BLAS thread each, private partial grids summed, then parallel degrid); kernel tables "
+                      f"built beforehand and not timed",
+            "seconds": dt_all,
+            "one_core": {"value": m / dt_one, "unit": "vis/s", "cores": 1, "rows": m, "seconds": dt_one}}
 
 
 if __name__ == "__main__":

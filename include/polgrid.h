@@ -75,6 +75,21 @@ extern "C" {
 #define PG_VARIANT_BANDED 8 /* pg_grid: force the row-band ownership kernel (no LDS atomics);
                                without either flag the library picks by sub-grid width.
                                Both give the same result up to float32 summation order. */
+#define PG_VARIANT_SHARED 32 /* pg_grid: force the shared-tap kernel: rows of one kernel phase share
+                                each tap load, and the sub-grid is summed in fixed point with LDS
+                                integer atomics (per item and plane, scaled from a bound on its
+                                values; inputs must be finite, an item with a non-finite
+                                visibility turns its grid points into NaN) */
+#define PG_DETERMINISTIC 16 /* pg_grid: bit-for-bit reproducible result.  Each work item's sub-grid
+                               is summed in a fixed order (row bands, 8 waves, all planes in one
+                               workgroup, whatever the plan's launch settings), and the sub-grids
+                               are added into 64-bit fixed-point accumulators with integer atomics,
+                               which do not depend on the order of the additions.  The fixed-point
+                               scale is a power of two chosen per call from a bound on every grid
+                               value (rows kept x largest row |vis|_1 x largest |re|+|im| of a
+                               table entry), so that no sum can overflow; inputs must be finite.
+                               Allocates npol * n * n * 16 bytes of device scratch per call
+                               (through the registered allocator).  Not with PG_VARIANT_ATOMIC. */
 
 /* pg_taper directions */
 #define PG_TAPER_IMAGE 0   /* complex FFT output -> real image / (AA(l) AA(m)) / weight_sum */
@@ -158,6 +173,11 @@ int pg_kernels_info(const pg_kernels* k, pg_kernels_desc* out);
 /* Copy the whole table (plane_offset[nplanes] entries of 8 bytes (F32) or 4 bytes (F16)) into
  * caller device memory `dst`; enqueue only. */
 int pg_kernels_copy_table(const pg_kernels* k, void* dst, void* stream);
+/* The inverse of pg_kernels_copy_table, for restoring a saved kernel set into one made by
+ * pg_kernels_alloc with the same spec: overwrite the whole table from caller device memory `src`
+ * (the same byte count and layout).  Call before the kernel set is shared.  Enqueue only.
+ * Errors: PG_EINVAL. */
+int pg_kernels_load_table(pg_kernels* k, const void* src, void* stream);
 void pg_kernels_destroy(pg_kernels* k);
 
 /* Visibility binning: float64 uvw -> fine positions, w-plane, anchor tile and
@@ -175,7 +195,8 @@ void pg_plan_destroy(pg_plan* p);
 
 /* Launch tuning of the kernels that run over this plan (results are unchanged up to float32
  * summation order): grid_variant 0 = choose by sub-grid width, 1 = LDS-atomic accumulation,
- * 2 = row-band ownership; grid_waves and degrid_waves = waves per workgroup, 4, 6, 8 or 16;
+ * 2 = row-band ownership, 3 = shared taps with fixed-point LDS accumulation (PG_VARIANT_SHARED);
+ * grid_waves and degrid_waves = waves per workgroup, 4, 6, 8 or 16;
  * xcd_group = how many consecutive work items (in plan order) run on one XCD, so that they share
  * its L2 (1 = plain order, up to 4096); grid_planes = output correlation planes per row-band
  * workgroup, 0 (all), 1, 2 or 4: with 1 or 2, npol / grid_planes workgroups share each work item,
@@ -191,7 +212,10 @@ int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int
 /* Gridding (Sec. 3.2, Sec. 4):
  *   G_q(X,Y) (+)= sum_k sum_c T_{p_k,q,c}(X os - fine_x,k, Y os - fine_y,k) V_{k,c}.
  * vis: complex64 [nvis][npol] (the plan's nvis); grid: complex64 [npol][n][n].
- * Without PG_ACCUMULATE the grid is overwritten.  Enqueue only. */
+ * Without PG_ACCUMULATE the grid is overwritten.  Enqueue only, except with PG_DETERMINISTIC,
+ * whose scratch is freed (stream-ordered through the registered allocator, else by hipFree, which
+ * waits for the device) before the call returns.  Errors: PG_EINVAL, PG_ENOMEM (deterministic
+ * scratch), PG_EHIP. */
 int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, int32_t flags,
             void* stream);
 
@@ -250,10 +274,14 @@ typedef struct pg_mlp pg_mlp;
 #define PG_MLP_GZ_BF16 10 /* its bfloat16 copy */
 #define PG_MLP_MW 11     /* float [d_in][d_out] Adam first moment of the layer's weights */
 #define PG_MLP_VW 12     /* float [d_in][d_out] Adam second moment of the layer's weights */
+#define PG_MLP_MB 13     /* float [d_out] Adam first moment of the layer's bias */
+#define PG_MLP_VB 14     /* float [d_out] Adam second moment of the layer's bias */
 
 int pg_mlp_create(int32_t n_in, int32_t width, int32_t hidden_layers, int64_t n_out, int32_t max_batch,
                   uint64_t seed, void* stream, pg_mlp** out);
-/* x: device float [batch][n_in]; y: device float [batch][n_out] or NULL.  Enqueue only. */
+/* x: device float [batch][n_in]; y: device float [batch][n_out], written directly by the output
+ * layer's product, or NULL to leave the output in the network's own buffer (PG_MLP_PRE of the
+ * output layer; with y given that buffer is not updated).  Enqueue only. */
 int pg_mlp_forward(pg_mlp* m, const float* x, int32_t batch, float* y, void* stream);
 /* Forward, loss, backward and (if update) one Adam step; loss_out: device float or NULL. */
 int pg_mlp_train_step(pg_mlp* m, const float* x, const float* target, int32_t batch, float lr, int32_t update,
@@ -262,7 +290,26 @@ int pg_mlp_train_step(pg_mlp* m, const float* x, const float* target, int32_t ba
 int pg_mlp_copy(const pg_mlp* m, int32_t what, int32_t layer, void* dst, void* stream);
 /* Set a layer's float weights [d_in][d_out] and bias [d_out] from device memory. */
 int pg_mlp_load(pg_mlp* m, int32_t layer, const float* w, const float* b, void* stream);
+/* Restore one piece of a layer's training state from device memory, for resuming from a saved
+ * checkpoint: what = PG_MLP_W (the bfloat16 copies are refreshed), PG_MLP_B, PG_MLP_MW, PG_MLP_VW,
+ * PG_MLP_MB or PG_MLP_VB, sizes as listed above.  Enqueue only.  Errors: PG_EINVAL. */
+int pg_mlp_set(pg_mlp* m, int32_t what, int32_t layer, const void* src, void* stream);
+/* Adam's step counter (the number of updates taken; bias corrections use it): read, or set when
+ * resuming (step >= 0).  Host calls.  Errors: PG_EINVAL. */
+int pg_mlp_get_step(const pg_mlp* m, int64_t* step);
+int pg_mlp_set_step(pg_mlp* m, int64_t step);
 void pg_mlp_destroy(pg_mlp* m);
+
+/* Float32 matrix product for the surrogate's training (its kernel basis, the projections of teacher
+ * kernels onto it and the fold of the output layer with it): C = alpha op(A) op(B) + beta C with
+ * row-major storage, op(X) = X (transX = 0) or X^T (transX != 0); op(A) is m x k, op(B) k x n, C
+ * m x n, leading dimensions lda, ldb, ldc (elements).  Float32 accumulation; deep contractions are
+ * split across workgroups and summed with float atomics (order of the partial sums varies).  All
+ * pointers device memory; enqueue only.  Errors: PG_EINVAL (sizes, leading dimensions, NULLs). */
+int pg_gemm_f32(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, float alpha, const float* a,
+                int64_t lda, const float* b, int64_t ldb, float beta, float* c, int64_t ldc, void* stream);
+/* x[r][c] *= scale[r] for a device float32 [rows][cols] matrix and device scale [rows]; enqueue only. */
+int pg_scale_rows(float* x, int64_t rows, int64_t cols, const float* scale, void* stream);
 
 /* ------------------------------------------------------------------ Hogbom minor cycle
  * The minor cycle of Cotton-Schwab clean (Sec. 2.1; Hogbom's algorithm), run on the device with no
@@ -284,6 +331,17 @@ void pg_mlp_destroy(pg_mlp* m);
 int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n, int32_t npol, float gain,
               float threshold, int32_t psf_patch, int32_t max_iter, int32_t* comp_pos, float* comp_val, float* model,
               int32_t* n_comp, void* stream);
+
+/* Peak search of a major cycle (Sec. 2.1): the largest |img[i]| over the pixels i < npix with
+ * mask[i] != 0 (mask NULL: all), and its index (the lowest on ties).  img float32 and mask uint8,
+ * device memory; peak and index host pointers, written before return (peak 0 and index -1 when no
+ * pixel is masked in).  Allocates 264 bytes of scratch per call; synchronises `stream`.
+ * Errors: PG_EINVAL, PG_ENOMEM, PG_EHIP. */
+int pg_masked_peak(const float* img, const uint8_t* mask, int64_t npix, float* peak, int64_t* index, void* stream);
+/* img[i] = img[i] / img[ref_index] for i < count, in place (e.g. a point-spread function scaled to
+ * one at the phase centre); the reference value is read before any pixel is divided.  Device
+ * memory; allocates 4 bytes of scratch per call; enqueue only.  Errors: PG_EINVAL, PG_ENOMEM. */
+int pg_normalise_at(float* img, int64_t count, int64_t ref_index, void* stream);
 
 /* pg_hogbom without any device allocation, for callers that cannot allocate: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, results and

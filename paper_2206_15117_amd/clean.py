@@ -4,7 +4,9 @@ components out of the residual image inside the beam mask; the model image is th
 through the degridding kernels and subtracted from the visibilities (taper x -1 -> inverse FFT
 -> accumulating degrid), and the next major cycle starts from the new residual.
 
-Every arithmetic step runs in the library's kernels; torch provides buffers and the FFT.
+Every arithmetic step of the cycles (imaging, peak search, PSF normalisation, minor cycles,
+prediction) runs in the library's kernels; torch provides buffers, the FFT and the AND of the
+two component masks when they are set up.
 """
 from __future__ import annotations
 
@@ -35,7 +37,7 @@ def psf(plan, kernels, weight_sum: float):
         unit[:, 3] = 1.0
     img = pg.image(plan, kernels, unit, weight_sum)[0].contiguous()
     n = img.shape[-1]
-    return img / img[n // 2, n // 2]
+    return pg.normalise_at(img, (n // 2) * n + n // 2)
 
 
 def taper_mask(kernels, aa_min: float = 0.1):
@@ -70,8 +72,7 @@ def cotton_schwab(plan, kernels_grid, kernels_degrid, vis, mask=None, gain: floa
     out = CleanResult(model=model, residual=None)
     for _ in range(cycles):
         img = pg.image(plan, kernels_grid, resid_vis, wsum, grid_buf=grid_buf)
-        i_abs = img[0].abs() if mask is None else img[0].abs() * mask
-        peak = float(i_abs.max())
+        peak, _ = pg.masked_peak(img[0], mask)
         out.peaks.append(peak)
         if peak < threshold:
             out.residual = img

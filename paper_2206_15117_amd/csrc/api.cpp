@@ -136,13 +136,15 @@ int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** ou
 
   const size_t entry = spec->storage == PG_STORE_F16 ? 4 : 8;
   if (!k->table.alloc(k->plane_offset.back() * entry, s) || !k->planes.alloc(sizeof(PlaneInfo) * g.nplanes, s) ||
-      !k->w_dev.alloc(sizeof(double) * g.nplanes, s) || !k->inv_aa.alloc(sizeof(double) * g.n, s))
+      !k->w_dev.alloc(sizeof(double) * g.nplanes, s) || !k->inv_aa.alloc(sizeof(double) * g.n, s) ||
+      !k->kbound.alloc(sizeof(float) * 4 * g.nplanes, s))
     return fail(PG_ENOMEM, "device allocation failed in make_kernels");
   PG_HIP(hipMemcpyAsync(k->planes.p, pinfo.data(), pinfo.size() * sizeof(PlaneInfo), hipMemcpyHostToDevice, s), "upload planes");
   PG_HIP(hipMemcpyAsync(k->w_dev.p, k->w_planes.data(), g.nplanes * sizeof(double), hipMemcpyHostToDevice, s), "upload w");
   PG_HIP(hipMemcpyAsync(k->inv_aa.p, inv_aa.data(), g.n * sizeof(double), hipMemcpyHostToDevice, s), "upload taper");
   if (!generate) {
     PG_HIP(hipMemsetAsync(k->table.p, 0, k->table.bytes, s), "clear table");
+    PG_HIP(launch_fill_zero(k->kbound.p, k->kbound.bytes, s), "clear bound");
     PG_HIP(hipStreamSynchronize(s), "kernels_alloc sync");
     *out = guard.release();
     return PG_OK;
@@ -172,6 +174,7 @@ int make_kernels_impl(const pg_kernel_spec* spec, hipStream_t s, pg_kernels** ou
     void* dst = static_cast<char*>(k->table.p) + k->plane_offset[p] * entry;
     PG_HIP(launch_pack(t_d.as<double2>(), S, g.os, nqc, spec->storage, dst, s), "pack");
   }
+  PG_HIP(refresh_kernel_bound(k, 0, g.nplanes, s), "kernel bound");
   PG_HIP(hipStreamSynchronize(s), "make_kernels sync");
   *out = guard.release();
   return PG_OK;
@@ -316,6 +319,15 @@ int pg_kernels_copy_table(const pg_kernels* k, void* dst, void* stream) {
   return PG_OK;
 }
 
+int pg_kernels_load_table(pg_kernels* k, const void* src, void* stream) {
+  g_error.clear();
+  if (!k || !src) return fail(PG_EINVAL, "kernels and src must be non-NULL");
+  PG_HIP(hipMemcpyAsync(k->table.p, src, k->table.bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+         "load table");
+  PG_HIP(refresh_kernel_bound(k, 0, k->nplanes, static_cast<hipStream_t>(stream)), "kernel bound");
+  return PG_OK;
+}
+
 void pg_kernels_destroy(pg_kernels* k) { delete k; }
 
 int pg_plan_create(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_chunk, void* stream,
@@ -358,7 +370,7 @@ int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int
                        int32_t xcd_group, int32_t grid_planes, int32_t degrid_corrs) {
   g_error.clear();
   if (!p) return fail(PG_EINVAL, "plan must be non-NULL");
-  if (grid_variant < 0 || grid_variant > 2) return fail(PG_EINVAL, "grid_variant must be 0, 1 or 2");
+  if (grid_variant < 0 || grid_variant > 3) return fail(PG_EINVAL, "grid_variant must be 0, 1, 2 or 3");
   auto ok = [](int w) { return w == 4 || w == 6 || w == 8 || w == 16; };
   if (!ok(grid_waves) || !ok(degrid_waves)) return fail(PG_EINVAL, "waves per workgroup must be 4, 6, 8 or 16");
   if (xcd_group < 1 || xcd_group > 4096) return fail(PG_EINVAL, "xcd_group must be in [1, 4096]");
@@ -377,11 +389,28 @@ int pg_plan_set_launch(pg_plan* p, int32_t grid_variant, int32_t grid_waves, int
 
 int pg_grid(const pg_plan* p, const pg_kernels* k, const void* vis, void* grid, int32_t flags, void* stream) {
   g_error.clear();
-  int rc = check_run(p, k, vis, grid, flags, PG_ACCUMULATE | PG_FFTSHIFT | PG_VARIANT_ATOMIC | PG_VARIANT_BANDED);
-  if ((flags & PG_VARIANT_ATOMIC) && (flags & PG_VARIANT_BANDED)) return fail(PG_EINVAL, "choose one grid variant");
+  int rc = check_run(p, k, vis, grid, flags,
+                     PG_ACCUMULATE | PG_FFTSHIFT | PG_VARIANT_ATOMIC | PG_VARIANT_BANDED | PG_VARIANT_SHARED |
+                         PG_DETERMINISTIC);
   if (rc != PG_OK) return rc;
-  PG_HIP(launch_grid(p, k, static_cast<const float2*>(vis), static_cast<float2*>(grid), flags,
-                     static_cast<hipStream_t>(stream)), "grid");
+  const int variants = ((flags & PG_VARIANT_ATOMIC) != 0) + ((flags & PG_VARIANT_BANDED) != 0) +
+                       ((flags & PG_VARIANT_SHARED) != 0);
+  if (variants > 1) return fail(PG_EINVAL, "choose one grid variant");
+  if ((flags & PG_DETERMINISTIC) && (flags & (PG_VARIANT_ATOMIC | PG_VARIANT_SHARED)))
+    return fail(PG_EINVAL, "PG_DETERMINISTIC uses the row-band kernel, not PG_VARIANT_ATOMIC or PG_VARIANT_SHARED");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (flags & PG_DETERMINISTIC) {
+    try {
+      DevBuf scratch;
+      if (!scratch.alloc(grid_fixed_scratch_bytes(k), s)) return fail(PG_ENOMEM, "device allocation failed in grid");
+      PG_HIP(launch_grid_fixed(p, k, static_cast<const float2*>(vis), static_cast<float2*>(grid), flags, scratch.p, s),
+             "deterministic grid");
+    } catch (...) {
+      return fail(PG_ENOMEM, "exception in grid");
+    }
+    return PG_OK;
+  }
+  PG_HIP(launch_grid(p, k, static_cast<const float2*>(vis), static_cast<float2*>(grid), flags, s), "grid");
   return PG_OK;
 }
 
@@ -631,6 +660,47 @@ int pg_hogbom(float* residual, const float* psf, const uint8_t* mask, int32_t n,
            "hogbom");
   } catch (...) {
     return fail(PG_ENOMEM, "exception in hogbom");
+  }
+  return PG_OK;
+}
+
+int pg_masked_peak(const float* img, const uint8_t* mask, int64_t npix, float* peak, int64_t* index, void* stream) {
+  g_error.clear();
+  if (!img || !peak || !index) return fail(PG_EINVAL, "img, peak and index must be non-NULL");
+  if (npix < 1 || npix > (int64_t(1) << 32) - 1) return fail(PG_EINVAL, "npix must be in [1, 2^32 - 1]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    DevBuf scratch;
+    if (!scratch.alloc(256 + 8, s)) return fail(PG_ENOMEM, "device allocation failed in masked_peak");
+    PG_HIP(launch_masked_peak(img, mask, npix, scratch.p, s), "masked peak");
+    unsigned long long key = 0;
+    PG_HIP(hipMemcpyAsync(&key, static_cast<char*>(scratch.p) + 256, 8, hipMemcpyDeviceToHost, s), "peak readback");
+    PG_HIP(hipStreamSynchronize(s), "peak sync");
+    if (key == 0) {
+      *peak = 0.0f;
+      *index = -1;
+    } else {
+      const uint32_t bits = static_cast<uint32_t>(key >> 32);
+      std::memcpy(peak, &bits, 4);
+      *index = static_cast<int64_t>(0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFFu));
+    }
+  } catch (...) {
+    return fail(PG_ENOMEM, "exception in masked_peak");
+  }
+  return PG_OK;
+}
+
+int pg_normalise_at(float* img, int64_t count, int64_t ref_index, void* stream) {
+  g_error.clear();
+  if (!img) return fail(PG_EINVAL, "img must be non-NULL");
+  if (count < 1 || ref_index < 0 || ref_index >= count) return fail(PG_EINVAL, "need 0 <= ref_index < count");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    DevBuf held;
+    if (!held.alloc(4, s)) return fail(PG_ENOMEM, "device allocation failed in normalise_at");
+    PG_HIP(launch_normalise_at(img, count, ref_index, held.as<float>(), s), "normalise");
+  } catch (...) {
+    return fail(PG_ENOMEM, "exception in normalise_at");
   }
   return PG_OK;
 }

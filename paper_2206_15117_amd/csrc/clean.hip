@@ -117,6 +117,19 @@ __global__ void clean_init_kernel(CleanState* st, unsigned long long* slots, int
 
 __global__ void clean_count_kernel(const CleanState* st, int32_t* n_comp) { *n_comp = st->ncomp; }
 
+// img[i] / ref for every pixel, ref = img[ref_index] read first into `held` (one thread), so the
+// division never sees a pixel already divided.
+__global__ void hold_value_kernel(const float* __restrict__ img, int64_t ref_index, float* __restrict__ held) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *held = img[ref_index];
+}
+
+__global__ void divide_by_held_kernel(float* __restrict__ img, int64_t count, const float* __restrict__ held) {
+  const float r = *held;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    img[i] = img[i] / r;
+}
+
 // Scratch of the allocation-free entry point: the iteration state (256 B) and one 64-bit peak
 // slot per iteration, for at most kStaticMaxIter iterations.  Each GPU holds its own copy; host
 // code reaches it only through the address hipGetSymbolAddress returns on that device.
@@ -143,6 +156,22 @@ hipError_t hogbom_static_scratch(void** out, size_t* bytes) {
   *out = g_static_ptr[dev];
   *bytes = kStaticScratchBytes;
   return hipSuccess;
+}
+
+hipError_t launch_masked_peak(const float* img, const uint8_t* mask, int64_t npix, void* scratch, hipStream_t s) {
+  auto* st = static_cast<CleanState*>(scratch);
+  auto* slot = reinterpret_cast<unsigned long long*>(static_cast<char*>(scratch) + 256);
+  hipLaunchKernelGGL(clean_init_kernel, dim3(1), dim3(64), 0, s, st, slot, 1);
+  const int blocks = static_cast<int>(std::min<int64_t>((npix + 255) / 256, 1024));
+  hipLaunchKernelGGL(peak_kernel, dim3(blocks), dim3(256), 0, s, img, mask, npix, slot, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalise_at(float* img, int64_t count, int64_t ref_index, float* held, hipStream_t s) {
+  hipLaunchKernelGGL(hold_value_kernel, dim3(1), dim3(64), 0, s, img, ref_index, held);
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((count + 255) / 256, 4096));
+  hipLaunchKernelGGL(divide_by_held_kernel, dim3(blocks), dim3(256), 0, s, img, count, held);
+  return hipGetLastError();
 }
 
 hipError_t launch_hogbom(float* residual, const float* psf, const uint8_t* mask, int n, int npol, float gain,

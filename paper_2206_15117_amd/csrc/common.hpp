@@ -131,6 +131,7 @@ struct pg_kernels {
   pg::DevBuf planes;                  // PlaneInfo [nplanes]
   pg::DevBuf w_dev;                   // double [nplanes]
   pg::DevBuf inv_aa;                  // double [n], 1 / AA(pixel)
+  pg::DevBuf kbound;                  // float [nplanes][4]: max over a plane's entries of Mueller row q of |re| + |im|
 };
 
 struct pg_plan {
@@ -197,11 +198,20 @@ hipError_t launch_grid(const pg_plan* p, const pg_kernels* k, const float2* vis,
                        hipStream_t s);
 hipError_t launch_degrid(const pg_plan* p, const pg_kernels* k, const float2* grid, float2* vis, int flags,
                          hipStream_t s);
+// Recompute kbound for planes [plane0, plane0 + nplanes) from the table (after any table write).
+hipError_t refresh_kernel_bound(pg_kernels* k, int plane0, int nplanes, hipStream_t s);
+// Reproducible gridding (PG_DETERMINISTIC) with caller-provided scratch of grid_fixed_scratch_bytes(k).
+size_t grid_fixed_scratch_bytes(const pg_kernels* k);
+hipError_t launch_grid_fixed(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
+                             void* scratch, hipStream_t s);
 hipError_t launch_taper(const pg_kernels* k, const void* in, void* out, int direction, double weight_sum,
                         hipStream_t s);
 hipError_t launch_hogbom(float* residual, const float* psf, const uint8_t* mask, int n, int npol, float gain,
                          float threshold, int patch, int max_iter, int32_t* comp_pos, float* comp_val, float* model,
                          int32_t* n_comp, void* scratch, hipStream_t s);
+// Masked |I| peak into the 64-bit key at scratch + 256 (scratch: 264 bytes); pixel normalisation.
+hipError_t launch_masked_peak(const float* img, const uint8_t* mask, int64_t npix, void* scratch, hipStream_t s);
+hipError_t launch_normalise_at(float* img, int64_t count, int64_t ref_index, float* held, hipStream_t s);
 // Device address (on the current device) and size of the fixed scratch array of pg_hogbom_noalloc.
 hipError_t hogbom_static_scratch(void** out, size_t* bytes);
 hipError_t launch_batch_grid(const pg_batch* b, int flags, hipStream_t s);

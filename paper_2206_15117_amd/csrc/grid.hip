@@ -252,6 +252,14 @@ __global__ __launch_bounds__(kThreads) void grid_kernel(const Item* __restrict__
   }
 }
 
+// Target of the reproducible flush: 64-bit fixed-point accumulators [q][n][n][re, im] and the
+// binary exponent that scales float sub-grid values into them.  Integer addition is associative,
+// so the accumulated bits do not depend on the order in which workgroups flush.
+struct FixedSink {
+  unsigned long long* acc;
+  const int* exp;
+};
+
 // One row (visibility) of a work item as one wave of the banded gridder sees it: the footprint rows
 // inside the wave's band [r0, r1), flattened to cnt = (b - a) S taps starting at tap t0, with the
 // row's visibility and kernel phase made wave-uniform (readlane of the lane that fetched them).
@@ -307,12 +315,12 @@ struct BandRow {
 // weighted by how many footprints of the item cover them); wave w owns band w and walks every
 // visibility of the item, taking only the footprint rows inside its band.  Bands are disjoint, so
 // the sub-grid (complex [q][W][P] in LDS) is updated with plain read-modify-write, no LDS atomics.
-template <int NP, typename TapT, int NW, bool PAIR, int NQ = NP>
+template <int NP, typename TapT, int NW, bool PAIR, int NQ = NP, bool FIXED = false>
 __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __restrict__ fine,
                                                  const int32_t* __restrict__ perm, const float2* __restrict__ vis,
                                                  const TapT* __restrict__ table, const PlaneInfo* __restrict__ planes,
                                                  int os, int n, float2* __restrict__ grid, int flags, int sub_bytes,
-                                                 float* lds_f, int q0 = 0) {
+                                                 float* lds_f, int q0 = 0, FixedSink fx = FixedSink{nullptr, nullptr}) {
   float2* lds = reinterpret_cast<float2*>(lds_f);
   int* rowload = reinterpret_cast<int*>(reinterpret_cast<char*>(lds_f) + sub_bytes);  // [W + 1]
   int* band = rowload + 256;                                                             // [NW + 1]
@@ -439,6 +447,8 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
   __syncthreads();
   const bool shift = (flags & PG_FFTSHIFT) != 0;
   const size_t pstride = static_cast<size_t>(n) * n;
+  int fe = 0;
+  if constexpr (FIXED) fe = __builtin_amdgcn_readfirstlane(*fx.exp);
   for (int idx = threadIdx.x; idx < W * W; idx += (NW * 64)) {
     const int y = idx / W, x = idx - y * W;
     const int X = it.ox + x, Y = it.oy + y;
@@ -449,9 +459,17 @@ __device__ __forceinline__ void grid_item_banded(const Item it, const int2* __re
     for (int q = 0; q < NQ; ++q) {
       const float2 g = lds[q * WP + l];
       if (g.x != 0.0f || g.y != 0.0f) {
-        float* gp = reinterpret_cast<float*>(grid + (q0 + q) * pstride + static_cast<size_t>(Y) * n + X);
-        unsafeAtomicAdd(gp, sg * g.x);
-        unsafeAtomicAdd(gp + 1, sg * g.y);
+        const size_t o = (q0 + q) * pstride + static_cast<size_t>(Y) * n + X;
+        if constexpr (FIXED) {
+          // |value| 2^fe < 2^61 by the choice of fe, so the rounded value converts exactly
+          atomicAdd(fx.acc + 2 * o, static_cast<unsigned long long>(static_cast<long long>(rintf(ldexpf(sg * g.x, fe)))));
+          atomicAdd(fx.acc + 2 * o + 1,
+                    static_cast<unsigned long long>(static_cast<long long>(rintf(ldexpf(sg * g.y, fe)))));
+        } else {
+          float* gp = reinterpret_cast<float*>(grid + o);
+          unsafeAtomicAdd(gp, sg * g.x);
+          unsafeAtomicAdd(gp + 1, sg * g.y);
+        }
       }
     }
   }
@@ -474,6 +492,292 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_kernel(const Item* __rest
   // two rows in flight costs registers: 1024-thread workgroups (capped at 128) take one at a time
   grid_item_banded<NP, TapT, NW, (NW <= 8), NQ>(items[item], fine, perm, vis, table, planes, os, n, grid, flags,
                                                 sub_bytes, lds_f, part * NQ);
+}
+
+// Shared-tap gridder.  Rows of a work item are phase-sorted inside the tile, so runs of rows share
+// one kernel phase: each wave takes a contiguous run of the item's rows and grids up to R rows of one
+// phase per pass, loading every tap once and applying it to all R rows, whose sub-grid positions
+// differ by wave-uniform offsets.  Waves overlap in the sub-grid, so it is accumulated with LDS
+// integer atomics (on CDNA4 these run at about the rate of plain LDS read-modify-write; float LDS
+// atomics are over an order of magnitude slower) in fixed point: output plane q of the item uses
+// the scale 2^e_q, B_q 2^e_q < 2^29, where B_q = kbound[plane][q] x the sum over the item's rows of
+// sum_c |Re V_c| + |Im V_c| bounds every sub-grid value of the plane and the sum of the magnitudes
+// of its terms, so no sum can overflow and one unit is at most B_q 2^-28: finer than float32
+// rounding of the terms it replaces.
+constexpr int kSharedScratch = 64;  // bytes after the sub-grid: the per-wave partial sums
+
+template <int NP, typename TapT, int R, int NQ>
+__device__ __forceinline__ void grid_rows_shared(int* lds, const TapT* __restrict__ pt, int j, int m_ly, int m_lx,
+                                                 int m_k, const float2* __restrict__ vis, int S, int SS, int P,
+                                                 int WP, float inv_s, const FootStep& step, int lane,
+                                                 const int (&ex)[NQ]) {
+  const TapChunks<NQ * NP, TapT> tc(pt, SS);
+  constexpr uint32_t TB = TapChunks<NQ * NP, TapT>::kTapBytes;
+  const int ly0 = __builtin_amdgcn_readlane(m_ly, j), lx0 = __builtin_amdgcn_readlane(m_lx, j);
+  int d[R];
+  float2 v[R][NP];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    d[r] = 2 * ((__builtin_amdgcn_readlane(m_ly, j + r) - ly0) * P + __builtin_amdgcn_readlane(m_lx, j + r) - lx0);
+    const int k = __builtin_amdgcn_readlane(m_k, j + r);
+#pragma unroll
+    for (int c = 0; c < NP; ++c) v[r][c] = vis[static_cast<size_t>(k) * NP + c];
+  }
+  TapCursor cur(lane, ly0, lx0, inv_s, S, P);
+  uint32_t boff = static_cast<uint32_t>(lane) * TB;
+  for (int t = lane; t < SS; t += 64) {
+    float2 tap[NQ * NP];
+    tc.load_at(boff, tap);
+    const int off = 2 * cur.off;
+    boff += 64 * TB;
+    cur.advance(step);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        float re = 0.0f, im = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+          const float2 a = tap[q * NP + c];
+          re = fmaf(a.x, v[r][c].x, fmaf(-a.y, v[r][c].y, re));
+          im = fmaf(a.x, v[r][c].y, fmaf(a.y, v[r][c].x, im));
+        }
+        int* cell = lds + 2 * q * WP + off + d[r];
+        atomicAdd(cell, __float2int_rn(ldexpf(re, ex[q])));
+        atomicAdd(cell + 1, __float2int_rn(ldexpf(im, ex[q])));
+      }
+    }
+  }
+}
+
+template <int NP, typename TapT, int NW, int NQ = NP>
+__device__ __forceinline__ void grid_item_shared(const Item it, const int2* __restrict__ fine,
+                                                 const int32_t* __restrict__ perm, const float2* __restrict__ vis,
+                                                 const TapT* __restrict__ table, const PlaneInfo* __restrict__ planes,
+                                                 const float* __restrict__ kbound, int os, int n,
+                                                 float2* __restrict__ grid, int flags, int sub_bytes, float* lds_f,
+                                                 int q0 = 0) {
+  int* lds = reinterpret_cast<int*>(lds_f);  // [q][W][P][re, im] fixed point
+  float* part = reinterpret_cast<float*>(reinterpret_cast<char*>(lds_f) + sub_bytes);  // [NW]
+  const PlaneInfo pl = planes[it.plane];
+  const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
+  const float inv_s = 1.0f / static_cast<float>(S);
+  for (int i = threadIdx.x; i < 2 * NQ * WP; i += NW * 64) lds[i] = 0;
+  // sum over the item's rows of sum_c |Re V_c| + |Im V_c|, the same float in every thread
+  float l1 = 0.0f;
+  for (int i = it.start + static_cast<int>(threadIdx.x); i < it.end; i += NW * 64) {
+    const size_t k = static_cast<size_t>(perm[i]);
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      const float2 a = vis[k * NP + c];
+      l1 += fabsf(a.x) + fabsf(a.y);
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  l1 = wave_sum_to_lane63(l1);
+  if (lane == 63) part[wave] = l1;
+  __syncthreads();
+  float total = 0.0f;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) total += part[w];
+  int ex[NQ];
+  bool finite = true;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const float b = kbound[4 * it.plane + q0 + q] * total;
+    int e2 = 0;
+    if (b > 0.0f && b <= 3.0e38f) {
+      frexpf(b, &e2);  // b < 2^e2
+      ex[q] = 29 - e2;
+    } else {
+      ex[q] = 0;
+      finite = finite && b == 0.0f;
+    }
+  }
+  const FootStep step(S, P);
+  const int per = (it.end - it.start + NW - 1) / NW;
+  const int w0 = it.start + wave * per, w1 = min(it.end, w0 + per);
+  for (int blk = w0; blk < w1 && finite; blk += 64) {
+    const int mine = blk + lane;
+    int m_ly = 0, m_lx = 0, m_ph = -1, m_k = 0;
+    if (mine < w1) {
+      const int2 f = fine[mine];
+      const int x0 = ceil_div_i(f.x - half + 1, os), y0 = ceil_div_i(f.y - half + 1, os);
+      m_ly = y0 - it.oy;
+      m_lx = x0 - it.ox;
+      m_ph = (y0 * os - f.y + half - 1) * os + (x0 * os - f.x + half - 1);
+      m_k = perm[mine];
+    }
+    const int nrow = min(64, w1 - blk);
+    for (int j = 0; j < nrow;) {
+      const int ph = __builtin_amdgcn_readlane(m_ph, j);
+      int run = 1;  // rows from j on with the same phase, up to 4
+      while (run < 4 && j + run < nrow && __builtin_amdgcn_readlane(m_ph, j + run) == ph) ++run;
+      run = __builtin_amdgcn_readfirstlane(run);
+      const TapT* pt = table + pl.offset + (static_cast<size_t>(ph) * NP * NP + q0 * NP) * SS;
+      if (run == 4) {
+        grid_rows_shared<NP, TapT, 4, NQ>(lds, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane, ex);
+      } else if (run >= 2) {
+        grid_rows_shared<NP, TapT, 2, NQ>(lds, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane, ex);
+        run = 2;
+      } else {
+        grid_rows_shared<NP, TapT, 1, NQ>(lds, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane, ex);
+      }
+      j += run;
+    }
+  }
+  __syncthreads();
+  const bool shift = (flags & PG_FFTSHIFT) != 0;
+  const size_t pstride = static_cast<size_t>(n) * n;
+  for (int idx = threadIdx.x; idx < W * W; idx += NW * 64) {
+    const int y = idx / W, x = idx - y * W;
+    const int X = it.ox + x, Y = it.oy + y;
+    if (X >= n || Y >= n) continue;
+    const int l = y * P + x;
+    const float sg = (shift && ((X + Y) & 1)) ? -1.0f : 1.0f;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      float* gp = reinterpret_cast<float*>(grid + (q0 + q) * pstride + static_cast<size_t>(Y) * n + X);
+      if (!finite) {  // a non-finite visibility or table bound: the item's points become NaN
+        unsafeAtomicAdd(gp, __int_as_float(0x7fc00000));
+        unsafeAtomicAdd(gp + 1, __int_as_float(0x7fc00000));
+        continue;
+      }
+      const int a = lds[2 * (q * WP + l)], b = lds[2 * (q * WP + l) + 1];
+      if (a != 0 || b != 0) {
+        unsafeAtomicAdd(gp, sg * ldexpf(static_cast<float>(a), -ex[q]));
+        unsafeAtomicAdd(gp + 1, sg * ldexpf(static_cast<float>(b), -ex[q]));
+      }
+    }
+  }
+}
+
+template <int NP, typename TapT, int NW, int NQ = NP>
+__global__ __launch_bounds__(NW * 64) void grid_shared_kernel(const Item* __restrict__ items,
+                                                              const int2* __restrict__ fine,
+                                                              const int32_t* __restrict__ perm,
+                                                              const float2* __restrict__ vis,
+                                                              const TapT* __restrict__ table,
+                                                              const PlaneInfo* __restrict__ planes,
+                                                              const float* __restrict__ kbound, int os, int n,
+                                                              float2* __restrict__ grid, int flags, int sub_bytes,
+                                                              int n_items, int group) {
+  extern __shared__ float lds_f[];
+  const int w = xcd_item(blockIdx.x, group);
+  const int item = w / (NP / NQ), part = w - item * (NP / NQ);
+  if (item >= n_items) return;
+  grid_item_shared<NP, TapT, NW, NQ>(items[item], fine, perm, vis, table, planes, kbound, os, n, grid, flags,
+                                     sub_bytes, lds_f, part * NQ);
+}
+
+// Reproducible gridding: one workgroup of 8 waves per work item, all planes, row bands (a fixed
+// summation order inside the item whatever the plan's launch settings), flushed into the
+// fixed-point accumulators.
+template <int NP, typename TapT>
+__global__ __launch_bounds__(512) void grid_fixed_kernel(const Item* __restrict__ items, const int2* __restrict__ fine,
+                                                         const int32_t* __restrict__ perm,
+                                                         const float2* __restrict__ vis,
+                                                         const TapT* __restrict__ table,
+                                                         const PlaneInfo* __restrict__ planes, int os, int n, int flags,
+                                                         int sub_bytes, FixedSink fx) {
+  extern __shared__ float lds_f[];
+  grid_item_banded<NP, TapT, 8, true, NP, true>(items[blockIdx.x], fine, perm, vis, table, planes, os, n, nullptr,
+                                                flags, sub_bytes, lds_f, 0, fx);
+}
+
+// Bounds for the fixed-point scale, as float bit patterns (non-negative floats order like their
+// bits, so an integer atomic max is exact and order-independent):
+//   bound[0] = max over kept rows of sum_c |re V_c| + |im V_c|
+//   bound[1] = max over table entries of |re T| + |im T|
+// |re (T V)| and |im (T V)| are at most (|re T| + |im T|)(|re V| + |im V|), so every grid value is
+// at most n_kept bound[0] bound[1].
+__device__ inline void wave_max_to(unsigned* out, float m) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void vis_bound_kernel(const int32_t* __restrict__ perm, int64_t n_kept, int np,
+                                 const float2* __restrict__ vis, unsigned* __restrict__ out) {
+  float m = 0.0f;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n_kept;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t k = perm[i];
+    float a = 0.0f;
+    for (int c = 0; c < np; ++c) {
+      const float2 v = vis[k * np + c];
+      a += fabsf(v.x) + fabsf(v.y);
+    }
+    m = fmaxf(m, a);
+  }
+  wave_max_to(out, m);
+}
+
+__device__ inline float2 tap_value(float2 t) { return t; }
+__device__ inline float2 tap_value(__half2 t) { return __half22float2(t); }
+
+template <typename TapT>
+__global__ void table_bound_kernel(const TapT* __restrict__ table, int64_t count, unsigned* __restrict__ out) {
+  float m = 0.0f;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float2 t = tap_value(table[i]);
+    m = fmaxf(m, fabsf(t.x) + fabsf(t.y));
+  }
+  wave_max_to(out, m);
+}
+
+// kbound[4 p + q] = max over the entries of Mueller row q in plane p's table of |re| + |im|.
+// Entry i of a plane: e = i mod E, tap = (i / E) mod SS, chunk = (i / (E SS)) mod (npol^2 / E);
+// Mueller cell q npol + c = chunk E + e.
+template <typename TapT>
+__global__ void kernel_bound_kernel(const TapT* __restrict__ plane_table, int64_t count, int ss, int e_per_chunk,
+                                    int npol, unsigned* __restrict__ out) {
+  float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int nch = npol * npol / e_per_chunk;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int e = static_cast<int>(i % e_per_chunk);
+    const int chunk = static_cast<int>((i / e_per_chunk / ss) % nch);
+    const int q = (chunk * e_per_chunk + e) / npol;
+    const float2 t = tap_value(plane_table[i]);
+    const float a = fabsf(t.x) + fabsf(t.y);
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+      if (qq == q) m[qq] = fmaxf(m[qq], a);
+  }
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) wave_max_to(out + qq, m[qq]);
+}
+
+// Binary exponent e with n_kept bound[0] bound[1] 2^e < 2^61: two bits of headroom below the int64
+// range for the float rounding inside the sub-grid sums.  Zero when the bound is zero.
+__global__ void fixed_exponent_kernel(const unsigned* __restrict__ bound, double n_kept, int* __restrict__ exp) {
+  const double b = n_kept * static_cast<double>(__uint_as_float(bound[0])) * static_cast<double>(__uint_as_float(bound[1]));
+  int e = 0;
+  if (b > 0.0 && b <= 1.0e300) {
+    int ex = 0;
+    frexp(b, &ex);  // b < 2^ex
+    e = 61 - ex;
+  }
+  *exp = e;
+}
+
+// grid (=, or += with accumulate) acc 2^-e, rounded once to float64 and once to float32.
+__global__ void fixed_to_grid_kernel(const unsigned long long* __restrict__ acc, const int* __restrict__ exp,
+                                     size_t count, float2* __restrict__ grid, int accumulate) {
+  const int e = *exp;
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const float re = static_cast<float>(ldexp(static_cast<double>(static_cast<long long>(acc[2 * i])), -e));
+    const float im = static_cast<float>(ldexp(static_cast<double>(static_cast<long long>(acc[2 * i + 1])), -e));
+    if (accumulate) {
+      const float2 g = grid[i];
+      grid[i] = make_float2(g.x + re, g.y + im);
+    } else {
+      grid[i] = make_float2(re, im);
+    }
+  }
 }
 
 // The batch field table is read through the constant address space: the compiler then takes the
@@ -719,6 +1023,31 @@ hipError_t run_grid_banded(const pg_plan* p, const pg_kernels* k, const float2* 
   return hipGetLastError();
 }
 
+template <int NP, typename TapT, int NW, int NQ = NP>
+hipError_t run_grid_shared(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
+                           hipStream_t s) {
+  auto fn = grid_shared_kernel<NP, TapT, NW, NQ>;
+  const size_t sub = k->lds_bytes / NP * NQ;
+  const size_t bytes = sub + kSharedScratch;
+  hipError_t e = allow_lds(fn, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(xcd_blocks(p->n_items * (NP / NQ), p->xcd_group)), dim3(NW * 64), bytes, s,
+                     p->items.as<Item>(), p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(),
+                     k->planes.as<PlaneInfo>(), k->kbound.as<float>(), k->os, k->n, grid, flags,
+                     static_cast<int>(sub), static_cast<int>(p->n_items), p->xcd_group);
+  return hipGetLastError();
+}
+
+template <int NP, typename TapT, int NW>
+hipError_t run_grid_shared_planes(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
+                                  hipStream_t s) {
+  if constexpr (NP == 4) {
+    if (p->grid_planes == 2) return run_grid_shared<NP, TapT, NW, 2>(p, k, vis, grid, flags, s);
+    if (p->grid_planes == 1) return run_grid_shared<NP, TapT, NW, 1>(p, k, vis, grid, flags, s);
+  }
+  return run_grid_shared<NP, TapT, NW>(p, k, vis, grid, flags, s);
+}
+
 // Output planes per workgroup (the plan's grid_planes; 0 or npol: all).  With fewer, NP / NQ
 // workgroups share each work item, each accumulating NQ planes from its NQ rows of the Mueller
 // kernels: the sub-grid in LDS shrinks by NP / NQ, so more workgroups fit on a CU.
@@ -738,10 +1067,21 @@ hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, fl
   // Banded ownership needs enough sub-grid rows to give every wave a band; the LDS-atomic
   // variant serves narrow sub-grids.  The plan's launch setting or a call flag can force either.
   bool banded = k->max_width >= 2 * p->grid_waves;
+  bool shared = p->grid_variant == 3;
   if (p->grid_variant == 1) banded = false;
   if (p->grid_variant == 2) banded = true;
+  if (flags & (PG_VARIANT_ATOMIC | PG_VARIANT_BANDED)) shared = false;
   if (flags & PG_VARIANT_ATOMIC) banded = false;
   if (flags & PG_VARIANT_BANDED) banded = true;
+  if (flags & PG_VARIANT_SHARED) shared = true;
+  if (shared) {
+    switch (p->grid_waves) {
+      case 4: return run_grid_shared_planes<NP, TapT, 4>(p, k, vis, grid, flags, s);
+      case 6: return run_grid_shared_planes<NP, TapT, 6>(p, k, vis, grid, flags, s);
+      case 8: return run_grid_shared_planes<NP, TapT, 8>(p, k, vis, grid, flags, s);
+      default: return run_grid_shared_planes<NP, TapT, 16>(p, k, vis, grid, flags, s);
+    }
+  }
   if (banded) {
     switch (p->grid_waves) {
       case 4: return run_grid_banded_planes<NP, TapT, 4>(p, k, vis, grid, flags, s);
@@ -888,6 +1228,76 @@ hipError_t launch_grid(const pg_plan* p, const pg_kernels* k, const float2* vis,
   const bool f16 = k->storage == PG_STORE_F16;
   if (k->npol == 4) return f16 ? run_grid<4, __half2>(p, k, vis, grid, flags, s) : run_grid<4, float2>(p, k, vis, grid, flags, s);
   return f16 ? run_grid<1, __half2>(p, k, vis, grid, flags, s) : run_grid<1, float2>(p, k, vis, grid, flags, s);
+}
+
+hipError_t refresh_kernel_bound(pg_kernels* k, int plane0, int nplanes, hipStream_t s) {
+  if (nplanes <= 0) return hipSuccess;
+  hipError_t e = launch_fill_zero(k->kbound.as<float>() + 4 * plane0, sizeof(float) * 4 * nplanes, s);
+  if (e != hipSuccess) return e;
+  const int nqc = k->npol * k->npol;
+  const int ec = chunk_entries(k->storage, nqc);
+  for (int p = plane0; p < plane0 + nplanes; ++p) {
+    const int64_t count = k->plane_offset[p + 1] - k->plane_offset[p];
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((count + 255) / 256, 2048));
+    unsigned* out = reinterpret_cast<unsigned*>(k->kbound.as<float>() + 4 * p);
+    const int ss = k->support[p] * k->support[p];
+    if (k->storage == PG_STORE_F16)
+      hipLaunchKernelGGL(kernel_bound_kernel<__half2>, dim3(blocks), dim3(256), 0, s,
+                         k->table.as<__half2>() + k->plane_offset[p], count, ss, ec, k->npol, out);
+    else
+      hipLaunchKernelGGL(kernel_bound_kernel<float2>, dim3(blocks), dim3(256), 0, s,
+                         k->table.as<float2>() + k->plane_offset[p], count, ss, ec, k->npol, out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t grid_fixed_scratch_bytes(const pg_kernels* k) {
+  return 256 + static_cast<size_t>(k->npol) * k->n * k->n * 2 * sizeof(unsigned long long);
+}
+
+namespace {
+template <int NP, typename TapT>
+hipError_t run_grid_fixed(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
+                          void* scratch, hipStream_t s) {
+  unsigned* bound = static_cast<unsigned*>(scratch);
+  int* exp = reinterpret_cast<int*>(static_cast<char*>(scratch) + 8);
+  auto* acc = reinterpret_cast<unsigned long long*>(static_cast<char*>(scratch) + 256);
+  const size_t count = static_cast<size_t>(k->npol) * k->n * k->n;
+  hipError_t e = launch_fill_zero(scratch, grid_fixed_scratch_bytes(k), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(vis_bound_kernel, dim3(static_cast<unsigned>(std::min<int64_t>((p->n_kept + 255) / 256, 4096))),
+                     dim3(256), 0, s, p->perm.as<int32_t>(), p->n_kept, NP, vis, bound);
+  const int64_t entries = k->plane_offset.back();
+  hipLaunchKernelGGL(table_bound_kernel<TapT>, dim3(static_cast<unsigned>(std::min<int64_t>((entries + 255) / 256, 8192))),
+                     dim3(256), 0, s, k->table.as<TapT>(), entries, bound + 1);
+  hipLaunchKernelGGL(fixed_exponent_kernel, dim3(1), dim3(1), 0, s, bound, static_cast<double>(p->n_kept), exp);
+  auto fn = grid_fixed_kernel<NP, TapT>;
+  const size_t bytes = k->lds_bytes + kBandScratch;
+  e = allow_lds(fn, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(512), bytes, s, p->items.as<Item>(),
+                     p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(), k->planes.as<PlaneInfo>(),
+                     k->os, k->n, flags, static_cast<int>(k->lds_bytes), FixedSink{acc, exp});
+  hipLaunchKernelGGL(fixed_to_grid_kernel, dim3(static_cast<unsigned>(std::min<size_t>((count + 255) / 256, 16384))),
+                     dim3(256), 0, s, acc, exp, count, grid, (flags & PG_ACCUMULATE) ? 1 : 0);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_grid_fixed(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
+                             void* scratch, hipStream_t s) {
+  if (p->n_items == 0) {
+    if (flags & PG_ACCUMULATE) return hipSuccess;
+    return launch_fill_zero(grid, static_cast<size_t>(k->npol) * k->n * k->n * sizeof(float2), s);
+  }
+  const bool f16 = k->storage == PG_STORE_F16;
+  if (k->npol == 4)
+    return f16 ? run_grid_fixed<4, __half2>(p, k, vis, grid, flags, scratch, s)
+               : run_grid_fixed<4, float2>(p, k, vis, grid, flags, scratch, s);
+  return f16 ? run_grid_fixed<1, __half2>(p, k, vis, grid, flags, scratch, s)
+             : run_grid_fixed<1, float2>(p, k, vis, grid, flags, scratch, s);
 }
 
 hipError_t launch_degrid(const pg_plan* p, const pg_kernels* k, const float2* grid, float2* vis, int flags,

@@ -99,7 +99,21 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
                                                         const float* __restrict__ bias, uint16_t* __restrict__ act) {
   __shared__ __attribute__((aligned(16))) uint16_t as[2][BM * LP];
   __shared__ __attribute__((aligned(16))) uint16_t bs[2][BN * LP];
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  // Workgroups are dealt to the 8 XCDs round-robin in launch order (x fastest), so with the plain
+  // mapping the M tiles that share a B tile land on every XCD and each XCD's L2 fetches every B
+  // tile.  When the tile count allows, XCD x takes the x-th contiguous eighth of the tiles (M tile
+  // fastest): each B tile is then read into one L2 only.
+  int mt = blockIdx.x, nt = blockIdx.y;
+  {
+    const int ntiles = gridDim.x * gridDim.y;
+    if ((ntiles & 7) == 0 && ntiles >= 64) {
+      const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+      const int logical = (lin & 7) * (ntiles >> 3) + (lin >> 3);
+      mt = logical % gridDim.x;
+      nt = logical / gridDim.x;
+    }
+  }
+  const int m0 = mt * BM, n0 = nt * BN;
   const int kb = blockIdx.z * ksplit, ke = min(K, kb + ksplit);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -177,6 +191,85 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
           }
         }
       }
+}
+
+// FP32 GEMM on the vector ALU for the surrogate's basis, projections and fold (float32 data,
+// float32 accumulation): C = alpha op(A) op(B) (+ beta C), row-major, op = identity or transpose.
+// 64 x 64 output tile per 256-thread workgroup, 4 x 4 per thread, k in steps of 16 staged in LDS as
+// [k][row] (rows contiguous) so each thread reads its four rows and four columns as float4; a split
+// contraction (gridDim.z > 1) adds alpha-scaled partial tiles atomically onto C.
+constexpr int SG = 64, SK = 16, SP = SG + 4;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void sgemm_kernel(int64_t M, int64_t N, int64_t K, float alpha,
+                                                    const float* __restrict__ A, int64_t lda,
+                                                    const float* __restrict__ B, int64_t ldb, float beta,
+                                                    float* __restrict__ C, int64_t ldc, int64_t ksplit) {
+  __shared__ __attribute__((aligned(16))) float as[SK][SP];
+  __shared__ __attribute__((aligned(16))) float bs[SK][SP];
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * SG, n0 = static_cast<int64_t>(blockIdx.y) * SG;
+  const int64_t kb = static_cast<int64_t>(blockIdx.z) * ksplit, ke = min(K, kb + ksplit);
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  float acc[4][4] = {};
+  for (int64_t k0 = kb; k0 < ke; k0 += SK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + i * 256;
+      // A tile: element (m, k); k-contiguous (TA false) or m-contiguous (TA true) in memory
+      const int am = TA ? e & 63 : e >> 4, ak = TA ? e >> 6 : e & 15;
+      const int64_t gm = m0 + am, gk = k0 + ak;
+      as[ak][am] = (gm < M && gk < ke) ? (TA ? A[gk * lda + gm] : A[gm * lda + gk]) : 0.0f;
+      // B tile: element (k, n); n-contiguous (TB false) or k-contiguous (TB true)
+      const int bn = TB ? e >> 4 : e & 63, bk = TB ? e & 15 : e >> 6;
+      const int64_t gn = n0 + bn, gk2 = k0 + bk;
+      bs[bk][bn] = (gn < N && gk2 < ke) ? (TB ? B[gn * ldb + gk2] : B[gk2 * ldb + gn]) : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < SK; ++kk) {
+      const float4 a = *reinterpret_cast<const float4*>(&as[kk][ty * 4]);
+      const float4 b = *reinterpret_cast<const float4*>(&bs[kk][tx * 4]);
+      const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = m0 + ty * 4 + i;
+    if (row >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = n0 + tx * 4 + j;
+      if (col >= N) continue;
+      float* c = C + row * ldc + col;
+      if (gridDim.z > 1) {
+        unsafeAtomicAdd(c, alpha * acc[i][j]);
+      } else {
+        *c = beta == 0.0f ? alpha * acc[i][j] : fmaf(beta, *c, alpha * acc[i][j]);
+      }
+    }
+  }
+}
+
+__global__ void scale_matrix_kernel(float* __restrict__ c, int64_t rows, int64_t cols, int64_t ldc, float beta) {
+  const int64_t n = rows * cols;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float* p = c + (i / cols) * ldc + i % cols;
+    *p = beta == 0.0f ? 0.0f : beta * *p;
+  }
+}
+
+// x[r][c] *= scale[r]
+__global__ void scale_rows_kernel(float* __restrict__ x, int64_t rows, int64_t cols, const float* __restrict__ scale) {
+  const int64_t n = rows * cols;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    x[i] *= scale[i / cols];
 }
 
 // Transpose of a bf16 matrix: out[c][r] = in[r][c], in [rows][cols]; 32 x 32 tiles through LDS.
@@ -350,6 +443,40 @@ hipError_t mlp_gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t
   if (b_k)
     return launch_gemm_epi<false, true>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, accumulate, bias, act, vec, s);
   return launch_gemm_epi<false, false>(M, N, K, A, lda, B, ldb, C, ldc, ksplit, nz, accumulate, bias, act, vec, s);
+}
+
+hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                    const float* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t tiles = ((M + SG - 1) / SG) * ((N + SG - 1) / SG);
+  // split a deep contraction when the output tiles alone cannot fill the GPU (about 1024 workgroups)
+  int64_t nz = 1;
+  if (tiles < 1024 && K >= 2048) nz = std::min<int64_t>((1024 + tiles - 1) / tiles, K / 1024);
+  nz = std::max<int64_t>(1, std::min<int64_t>(nz, 1024));
+  const int64_t ksplit = ((K + nz - 1) / nz + SK - 1) / SK * SK;
+  nz = K > 0 ? (K + ksplit - 1) / ksplit : 1;
+  if (nz > 1 || K <= 0) {  // partial tiles go onto beta C
+    hipLaunchKernelGGL(scale_matrix_kernel, grid_1d(M * N), dim3(256), 0, s, C, M, N, ldc, beta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || K <= 0) return e;
+  }
+  dim3 grid(static_cast<unsigned>((M + SG - 1) / SG), static_cast<unsigned>((N + SG - 1) / SG),
+            static_cast<unsigned>(nz));
+  if (ta && tb)
+    hipLaunchKernelGGL((sgemm_kernel<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ksplit);
+  else if (ta)
+    hipLaunchKernelGGL((sgemm_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ksplit);
+  else if (tb)
+    hipLaunchKernelGGL((sgemm_kernel<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ksplit);
+  else
+    hipLaunchKernelGGL((sgemm_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ksplit);
+  return hipGetLastError();
+}
+
+hipError_t scale_rows(float* x, int64_t rows, int64_t cols, const float* scale, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_rows_kernel, grid_1d(rows * cols), dim3(256), 0, s, x, rows, cols, scale);
+  return hipGetLastError();
 }
 
 hipError_t mlp_transpose_bf16(const uint16_t* in, int64_t rows, int64_t cols, uint16_t* out, hipStream_t s) {

@@ -10,6 +10,9 @@ namespace pg {
 hipError_t mlp_gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
                     int64_t sbn, float* C, int64_t ldc, bool accumulate, int split_k, hipStream_t s,
                     const float* bias = nullptr, uint16_t* act = nullptr);
+hipError_t gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                    const float* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s);
+hipError_t scale_rows(float* x, int64_t rows, int64_t cols, const float* scale, hipStream_t s);
 hipError_t mlp_transpose_bf16(const uint16_t* in, int64_t rows, int64_t cols, uint16_t* out, hipStream_t s);
 hipError_t mlp_silu_back(const float* gact, const float* z, int64_t n, float* gpre, uint16_t* gpre_bf, hipStream_t s);
 hipError_t mlp_loss(const float* y, const float* t, int64_t cols, int batch, float* grad, uint16_t* grad_bf,

@@ -50,15 +50,17 @@ int split_for(int64_t M, int64_t N, int64_t K) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(split, 256)));
 }
 
-int forward_impl(pg_mlp* m, const float* x, int batch, hipStream_t s) {
+// y: where the output layer writes (NULL: the network's own pre-activation buffer, which the
+// training step reads).
+int forward_impl(pg_mlp* m, const float* x, int batch, hipStream_t s, float* y = nullptr) {
   const int L = static_cast<int>(m->layers.size());
   PGM_HIP(pg::mlp_to_bf16(x, static_cast<int64_t>(batch) * m->n_in, m->x_bf.as<uint16_t>(), s), "features");
   const uint16_t* a = m->x_bf.as<uint16_t>();
   for (int l = 0; l < L; ++l) {
     const int64_t din = m->dims[l], dout = m->dims[l + 1];
-    float* z = m->pre[l].as<float>();
-    // z = a W + b, and for hidden layers SiLU(z) in bf16, in the product's epilogue
     const bool hidden = l + 1 < L;
+    float* z = (!hidden && y) ? y : m->pre[l].as<float>();
+    // z = a W + b, and for hidden layers SiLU(z) in bf16, in the product's epilogue
     PGM_HIP(pg::mlp_gemm(batch, static_cast<int>(dout), static_cast<int>(din), a, din, 1, m->layers[l].w_bft.as<uint16_t>(),
                          1, din, z, dout, false, 1, s, m->layers[l].b.as<float>(),
                          hidden ? m->act[l].as<uint16_t>() : nullptr),
@@ -128,12 +130,7 @@ int pg_mlp_forward(pg_mlp* m, const float* x, int32_t batch, float* y, void* str
   if (!m || !x) return fail(PG_EINVAL, "network and features must be non-NULL");
   if (batch < 1 || batch > m->max_batch) return fail(PG_EINVAL, "batch must be in [1, max_batch]");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int rc = forward_impl(m, x, batch, s);
-  if (rc != PG_OK) return rc;
-  if (y)
-    PGM_HIP(hipMemcpyAsync(y, m->pre.back().p, 4 * static_cast<int64_t>(batch) * m->n_out, hipMemcpyDeviceToDevice, s),
-            "copy output");
-  return PG_OK;
+  return forward_impl(m, x, batch, s, y);
 }
 
 int pg_mlp_train_step(pg_mlp* m, const float* x, const float* target, int32_t batch, float lr, int32_t update,
@@ -212,6 +209,8 @@ int pg_mlp_copy(const pg_mlp* m, int32_t what, int32_t layer, void* dst, void* s
     case PG_MLP_GZ_BF16: src = m->gz_bf.p; bytes = 2 * B * m->dims[1]; break;
     case PG_MLP_MW: src = ly.mw.p; bytes = 4 * din * dout; break;
     case PG_MLP_VW: src = ly.vw.p; bytes = 4 * din * dout; break;
+    case PG_MLP_MB: src = ly.mb.p; bytes = 4 * dout; break;
+    case PG_MLP_VB: src = ly.vb.p; bytes = 4 * dout; break;
     default: return fail(PG_EINVAL, "unknown quantity");
   }
   PGM_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)), "copy");
@@ -233,7 +232,71 @@ int pg_mlp_load(pg_mlp* m, int32_t layer, const float* w, const float* b, void* 
   return PG_OK;
 }
 
+int pg_mlp_set(pg_mlp* m, int32_t what, int32_t layer, const void* src, void* stream) {
+  pg::set_error("");
+  if (!m || !src) return fail(PG_EINVAL, "network and src must be non-NULL");
+  if (layer < 0 || layer >= static_cast<int>(m->layers.size())) return fail(PG_EINVAL, "layer out of range");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto& ly = m->layers[layer];
+  const int64_t din = m->dims[layer], dout = m->dims[layer + 1];
+  pg::DevBuf* dst = nullptr;
+  int64_t bytes = 0;
+  switch (what) {
+    case PG_MLP_W: dst = &ly.w; bytes = 4 * din * dout; break;
+    case PG_MLP_B: dst = &ly.b; bytes = 4 * dout; break;
+    case PG_MLP_MW: dst = &ly.mw; bytes = 4 * din * dout; break;
+    case PG_MLP_VW: dst = &ly.vw; bytes = 4 * din * dout; break;
+    case PG_MLP_MB: dst = &ly.mb; bytes = 4 * dout; break;
+    case PG_MLP_VB: dst = &ly.vb; bytes = 4 * dout; break;
+    default: return fail(PG_EINVAL, "settable: PG_MLP_W, PG_MLP_B and the Adam moments");
+  }
+  PGM_HIP(hipMemcpyAsync(dst->p, src, bytes, hipMemcpyDeviceToDevice, s), "set");
+  if (what == PG_MLP_W) {
+    PGM_HIP(pg::mlp_to_bf16(ly.w.as<float>(), din * dout, ly.w_bf.as<uint16_t>(), s), "set bf16");
+    PGM_HIP(pg::mlp_transpose_bf16(ly.w_bf.as<uint16_t>(), din, dout, ly.w_bft.as<uint16_t>(), s), "set transpose");
+  }
+  return PG_OK;
+}
+
+int pg_mlp_get_step(const pg_mlp* m, int64_t* step) {
+  pg::set_error("");
+  if (!m || !step) return fail(PG_EINVAL, "network and step must be non-NULL");
+  *step = m->step;
+  return PG_OK;
+}
+
+int pg_mlp_set_step(pg_mlp* m, int64_t step) {
+  pg::set_error("");
+  if (!m) return fail(PG_EINVAL, "network must be non-NULL");
+  if (step < 0) return fail(PG_EINVAL, "step must be >= 0");
+  m->step = step;
+  return PG_OK;
+}
+
 void pg_mlp_destroy(pg_mlp* m) { delete m; }
+
+int pg_gemm_f32(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, float alpha, const float* a,
+                int64_t lda, const float* b, int64_t ldb, float beta, float* c, int64_t ldc, void* stream) {
+  pg::set_error("");
+  if (m < 0 || n < 0 || k < 0) return fail(PG_EINVAL, "m, n and k must be >= 0");
+  if ((m > 0 && n > 0) && !c) return fail(PG_EINVAL, "c must be non-NULL");
+  if (m > 0 && n > 0 && k > 0 && (!a || !b)) return fail(PG_EINVAL, "a and b must be non-NULL");
+  if (lda < (transa ? m : k) || ldb < (transb ? k : n) || ldc < n)
+    return fail(PG_EINVAL, "leading dimensions must cover a row of the stored matrix");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PG_EINVAL, "alpha and beta must be finite");
+  PGM_HIP(pg::gemm_f32(transa != 0, transb != 0, m, n, k, alpha, a, lda, b, ldb, beta, c, ldc,
+                       static_cast<hipStream_t>(stream)),
+          "gemm_f32");
+  return PG_OK;
+}
+
+int pg_scale_rows(float* x, int64_t rows, int64_t cols, const float* scale, void* stream) {
+  pg::set_error("");
+  if (rows < 0 || cols < 0) return fail(PG_EINVAL, "rows and cols must be >= 0");
+  if (rows > 0 && cols > 0 && (!x || !scale)) return fail(PG_EINVAL, "x and scale must be non-NULL");
+  PGM_HIP(pg::scale_rows(x, rows, cols, scale, static_cast<hipStream_t>(stream)), "scale_rows");
+  return PG_OK;
+}
 
 int pg_kernels_write_cell(pg_kernels* k, int32_t plane, int32_t q, int32_t c, const float* src, void* stream) {
   pg::set_error("");
@@ -247,6 +310,7 @@ int pg_kernels_write_cell(pg_kernels* k, int32_t plane, int32_t q, int32_t c, co
                       k->plane_offset[plane], 1, q * k->npol + c, 1, const_cast<float*>(src), true, one,
                       static_cast<hipStream_t>(stream)),
           "write cell");
+  PGM_HIP(pg::refresh_kernel_bound(k, plane, 1, static_cast<hipStream_t>(stream)), "kernel bound");
   return PG_OK;
 }
 
@@ -288,6 +352,7 @@ int pg_kernels_import(pg_kernels* k, int32_t plane0, int32_t nplanes, const floa
                       k->plane_offset[plane0], nplanes, 0, nqc, const_cast<float*>(src), true, sc,
                       static_cast<hipStream_t>(stream)),
           "import cells");
+  PGM_HIP(pg::refresh_kernel_bound(k, plane0, nplanes, static_cast<hipStream_t>(stream)), "kernel bound");
   return PG_OK;
 }
 

@@ -35,9 +35,10 @@ class Field:
 
 
 def image(fields, vis_list, mosaic_frame, min_weight: float, out=None, weight_out=None, grid_buf=None,
-          field_buf=None):
+          field_buf=None, deterministic: bool = False):
     """Mosaic of the fields' dirty images: sum_f w_f I_f / sum_f w_f on mosaic_frame (0 where the
-    total weight is below min_weight).  Returns (mosaic float32 [npol][n][n], weight [n][n])."""
+    total weight is below min_weight).  Returns (mosaic float32 [npol][n][n], weight [n][n]).
+    deterministic: field images gridded in the reproducible mode."""
     import torch
 
     npol = fields[0].kernels_grid.npol
@@ -50,7 +51,8 @@ def image(fields, vis_list, mosaic_frame, min_weight: float, out=None, weight_ou
     out.zero_()
     weight_out.zero_()
     for f, vis in zip(fields, vis_list):
-        img = pg.image(f.plan, f.kernels_grid, vis, f.weight_sum, grid_buf=grid_buf, out=field_buf)
+        img = pg.image(f.plan, f.kernels_grid, vis, f.weight_sum, grid_buf=grid_buf, out=field_buf,
+                       deterministic=deterministic)
         pg.reproject(img, f.frame, out, mosaic_frame, src_weight=f.weight, dst_weight=weight_out, accumulate=True)
     pg.weight_normalise(out, weight_out, min_weight)
     return out, weight_out

@@ -19,7 +19,7 @@ OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 KIND_GRID, KIND_DEGRID = 0, 1
 STORE_F32, STORE_F16 = 0, 1
 STOKES_IAU, STOKES_PAPER = 0, 1
-ACCUMULATE, FFTSHIFT, VARIANT_ATOMIC, VARIANT_BANDED = 1, 2, 4, 8
+ACCUMULATE, FFTSHIFT, VARIANT_ATOMIC, VARIANT_BANDED, DETERMINISTIC, VARIANT_SHARED = 1, 2, 4, 8, 16, 32
 TAPER_IMAGE, TAPER_PREDICT = 0, 1
 
 
@@ -64,6 +64,7 @@ EXPORTS = {
     "pg_make_kernels": (c_int, [POINTER(PgKernelSpec), c_void_p, POINTER(c_void_p)]),
     "pg_kernels_info": (c_int, [c_void_p, POINTER(PgKernelsDesc)]),
     "pg_kernels_copy_table": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "pg_kernels_load_table": (c_int, [c_void_p, c_void_p, c_void_p]),
     "pg_kernels_destroy": (None, [c_void_p]),
     "pg_plan_create": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, POINTER(c_void_p), POINTER(c_int64)]),
     "pg_plan_info": (c_int, [c_void_p, POINTER(PgPlanDesc)]),
@@ -89,8 +90,13 @@ EXPORTS = {
                           c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pg_hogbom_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float, ctypes.c_float,
                                   c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pg_masked_peak": (c_int, [c_void_p, c_void_p, c_int64, POINTER(ctypes.c_float), POINTER(c_int64), c_void_p]),
+    "pg_normalise_at": (c_int, [c_void_p, c_int64, c_int64, c_void_p]),
     "pg_mosaic_gamma": (c_int, [c_void_p, c_int32, c_int32, c_double, c_double, c_void_p, c_void_p, c_int32,
                                 c_void_p]),
+    "pg_gemm_f32": (c_int, [c_int32, c_int32, c_int64, c_int64, c_int64, ctypes.c_float, c_void_p, c_int64,
+                            c_void_p, c_int64, ctypes.c_float, c_void_p, c_int64, c_void_p]),
+    "pg_scale_rows": (c_int, [c_void_p, c_int64, c_int64, c_void_p, c_void_p]),
     "pg_kernels_export": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "pg_kernels_import": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "pg_mlp_create": (c_int, [c_int32, c_int32, c_int32, c_int64, c_int32, ctypes.c_uint64, c_void_p,
@@ -100,6 +106,9 @@ EXPORTS = {
                                   c_void_p]),
     "pg_mlp_copy": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "pg_mlp_load": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "pg_mlp_set": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+    "pg_mlp_get_step": (c_int, [c_void_p, POINTER(c_int64)]),
+    "pg_mlp_set_step": (c_int, [c_void_p, c_int64]),
     "pg_mlp_destroy": (None, [c_void_p]),
 }
 
@@ -183,7 +192,7 @@ def _geometry_struct(geom):
 
 
 (MLP_W, MLP_W_BF16, MLP_B, MLP_GW, MLP_GB, MLP_ACT, MLP_PRE, MLP_GY, MLP_GY_BF16, MLP_GZ, MLP_GZ_BF16, MLP_MW,
- MLP_VW) = range(13)
+ MLP_VW, MLP_MB, MLP_VB) = range(15)
 
 
 class Kernels:
@@ -214,6 +223,15 @@ class Kernels:
             out = torch.empty(n, dtype=torch.complex64, device="cuda")
         _check(lib().pg_kernels_copy_table(self._h, _ptr(out), _stream()))
         return out
+
+    def load_table(self, src, stream=None):
+        """Overwrite the whole table from a device tensor laid out as table() returns it."""
+        n = int(self.plane_offset[-1])
+        want = (n, 2) if self.storage == STORE_F16 else (n,)
+        dt = "torch.float16" if self.storage == STORE_F16 else "torch.complex64"
+        if tuple(src.shape) != want or str(src.dtype) != dt or not src.is_contiguous():
+            raise ValueError(f"src must be a contiguous {dt} tensor of shape {want}")
+        _check(lib().pg_kernels_load_table(self._h, _ptr(src), _stream(stream)))
 
     def write_cell(self, plane: int, q: int, c: int, src, stream=None):
         """Overwrite cell (q, c) of `plane` from device float [os][os][S][S][2]."""
@@ -307,7 +325,7 @@ class Plan:
 
     def set_launch(self, grid_variant: int = 0, grid_waves: int = 16, degrid_waves: int = 16, xcd_group: int = 1,
                    grid_planes: int = 0, degrid_corrs: int = 0):
-        """Launch tuning (grid variant 0 auto / 1 atomic / 2 banded, waves per workgroup, consecutive
+        """Launch tuning (grid variant 0 auto / 1 atomic / 2 banded / 3 shared taps, waves per workgroup, consecutive
         work items per XCD, output planes per banded-gridder workgroup: 0 = all, 1, 2 or 4, output
         correlations per degrid workgroup: 0 = all, 2 or 4)."""
         _check(lib().pg_plan_set_launch(self._h, int(grid_variant), int(grid_waves), int(degrid_waves),
@@ -337,7 +355,9 @@ def _grid_shape(k: Kernels):
 
 
 def grid(p: Plan, k: Kernels, vis, out=None, accumulate: bool = False, fftshift: bool = False, stream=None,
-         variant: int = 0):
+         variant: int = 0, deterministic: bool = False):
+    """Grid `vis` [nvis, npol] onto `out` [npol, n, n].  deterministic=True gives bit-for-bit
+    reproducible grids (fixed-point accumulation; allocates npol n^2 16 bytes of scratch per call)."""
     import torch
 
     if vis.dtype != torch.complex64 or not vis.is_contiguous() or tuple(vis.shape) != (p.nvis, k.npol):
@@ -346,7 +366,8 @@ def grid(p: Plan, k: Kernels, vis, out=None, accumulate: bool = False, fftshift:
         out = torch.empty(_grid_shape(k), dtype=torch.complex64, device=vis.device)
     elif out.dtype != torch.complex64 or tuple(out.shape) != _grid_shape(k) or not out.is_contiguous():
         raise ValueError("out must be contiguous complex64 [npol, n, n]")
-    flags = (ACCUMULATE if accumulate else 0) | (FFTSHIFT if fftshift else 0) | int(variant)
+    flags = (ACCUMULATE if accumulate else 0) | (FFTSHIFT if fftshift else 0) | int(variant) | \
+        (DETERMINISTIC if deterministic else 0)
     _check(lib().pg_grid(p.handle, k.handle, _ptr(vis), _ptr(out), flags, _stream(stream)))
     return out
 
@@ -389,11 +410,12 @@ def taper(k: Kernels, inp, out, direction: int, weight_sum: float = 1.0, stream=
     return out
 
 
-def image(p: Plan, k: Kernels, vis, weight_sum: float, grid_buf=None, out=None):
-    """Dirty image: grid (centring folded in) -> FFT (rocFFT via torch) -> taper correction."""
+def image(p: Plan, k: Kernels, vis, weight_sum: float, grid_buf=None, out=None, deterministic: bool = False):
+    """Dirty image: grid (centring folded in) -> FFT (rocFFT via torch) -> taper correction.
+    deterministic: grid in the reproducible mode (the same image bits on every call)."""
     import torch
 
-    g = grid(p, k, vis, out=grid_buf, fftshift=True)
+    g = grid(p, k, vis, out=grid_buf, fftshift=True, deterministic=deterministic)
     f = torch.fft.fft2(g)
     if out is None:
         out = torch.empty(_grid_shape(k), dtype=torch.float32, device=vis.device)
@@ -507,6 +529,31 @@ def hogbom(residual, psf, mask=None, gain: float = 0.1, threshold: float = 0.0, 
     return pos[:m], val[:m]
 
 
+def masked_peak(img, mask=None, stream=None):
+    """(largest |img| over the mask, its flat index) by pg_masked_peak; img float32, mask uint8 of
+    the same number of elements (None: all).  (0.0, -1) when no pixel is masked in."""
+    import torch
+
+    if img.dtype != torch.float32 or not img.is_contiguous():
+        raise ValueError("img must be contiguous float32")
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != img.numel() or not mask.is_contiguous()):
+        raise ValueError("mask must be contiguous uint8 with img's number of elements")
+    peak, index = ctypes.c_float(), c_int64()
+    _check(lib().pg_masked_peak(_ptr(img), _ptr(mask), img.numel(), ctypes.byref(peak), ctypes.byref(index),
+                                _stream(stream)))
+    return float(peak.value), int(index.value)
+
+
+def normalise_at(img, ref_index: int, stream=None):
+    """img /= img.flatten()[ref_index] in place (pg_normalise_at); img contiguous float32."""
+    import torch
+
+    if img.dtype != torch.float32 or not img.is_contiguous():
+        raise ValueError("img must be contiguous float32")
+    _check(lib().pg_normalise_at(_ptr(img), img.numel(), int(ref_index), _stream(stream)))
+    return img
+
+
 def mosaic_gamma(beams, img, floor: float = 1e-3, scale: float = 0.5, weight_sum=None, stream=None):
     """UV-domain mosaic correction (pg_mosaic_gamma, Eq. 1): img float32 [npol, n, n] is multiplied in
     place by scale x gamma from the fields' power beams float32 [nfields, n, n]; returns S = sum B^2."""
@@ -557,6 +604,41 @@ def batch(fields, stream=None) -> Batch:
     return Batch(fields, stream)
 
 
+def gemm_f32(a, b, out=None, transa: bool = False, transb: bool = False, alpha: float = 1.0, beta: float = 0.0,
+             stream=None):
+    """out = alpha op(a) op(b) + beta out (pg_gemm_f32) for contiguous float32 2-D device tensors,
+    op(x) = x or x^T; out is allocated (and beta ignored) when None."""
+    import torch
+
+    for t, nm in ((a, "a"), (b, "b")):
+        if t.dtype != torch.float32 or t.dim() != 2 or not t.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous float32 matrix")
+    m, k = (a.shape[1], a.shape[0]) if transa else (a.shape[0], a.shape[1])
+    kb, n = (b.shape[1], b.shape[0]) if transb else (b.shape[0], b.shape[1])
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float32, device=a.device)
+        beta = 0.0
+    elif out.dtype != torch.float32 or tuple(out.shape) != (m, n) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous float32 [{m}, {n}] tensor")
+    _check(lib().pg_gemm_f32(int(bool(transa)), int(bool(transb)), m, n, k, ctypes.c_float(alpha), _ptr(a),
+                             a.shape[1], _ptr(b), b.shape[1], ctypes.c_float(beta), _ptr(out), n, _stream(stream)))
+    return out
+
+
+def scale_rows(x, scale, stream=None):
+    """x[r, :] *= scale[r] in place (pg_scale_rows) for contiguous float32 x [rows, cols], scale [rows]."""
+    import torch
+
+    if x.dtype != torch.float32 or x.dim() != 2 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 matrix")
+    if scale.dtype != torch.float32 or tuple(scale.shape) != (x.shape[0],) or not scale.is_contiguous():
+        raise ValueError("scale must be contiguous float32 [rows]")
+    _check(lib().pg_scale_rows(_ptr(x), x.shape[0], x.shape[1], _ptr(scale), _stream(stream)))
+    return x
+
+
 class MLP:
     """Kernel surrogate network (pg_mlp): BF16 matrix-core products, FP32 masters, Adam."""
 
@@ -566,13 +648,19 @@ class MLP:
                                    ctypes.c_uint64(int(seed)), _stream(stream), ctypes.byref(h)))
         self._h = h
         self.dims = [n_in] + [width] * hidden + [n_out]
+        self.n_in, self.width, self.hidden, self.n_out = int(n_in), int(width), int(hidden), int(n_out)
         self.max_batch = max_batch
 
     def forward(self, x, out=None, stream=None):
         import torch
 
+        if x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 2 or x.shape[1] != self.dims[0]:
+            raise ValueError(f"x must be contiguous float32 [batch, {self.dims[0]}]")
         if out is None:
             out = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device=x.device)
+        elif (out.dtype != torch.float32 or not out.is_contiguous()
+              or tuple(out.shape) != (x.shape[0], self.dims[-1])):
+            raise ValueError(f"out must be contiguous float32 [{x.shape[0]}, {self.dims[-1]}]")
         _check(lib().pg_mlp_forward(self._h, _ptr(x), int(x.shape[0]), _ptr(out), _stream(stream)))
         return out
 
@@ -595,7 +683,8 @@ class MLP:
                   MLP_PRE: ((batch, dout), torch.float32), MLP_GY: ((batch, self.dims[-1]), torch.float32),
                   MLP_GY_BF16: ((batch, self.dims[-1]), torch.bfloat16), MLP_GZ: ((batch, self.dims[1]), torch.float32),
                   MLP_GZ_BF16: ((batch, self.dims[1]), torch.bfloat16), MLP_MW: ((din, dout), torch.float32),
-                  MLP_VW: ((din, dout), torch.float32)}
+                  MLP_VW: ((din, dout), torch.float32), MLP_MB: ((dout,), torch.float32),
+                  MLP_VB: ((dout,), torch.float32)}
         shape, dt = shapes[what]
         out = torch.empty(shape, dtype=dt, device="cuda")
         _check(lib().pg_mlp_copy(self._h, int(what), int(layer), _ptr(out), _stream()))
@@ -603,6 +692,27 @@ class MLP:
 
     def load(self, layer: int, w, b):
         _check(lib().pg_mlp_load(self._h, int(layer), _ptr(w.contiguous()), _ptr(b.contiguous()), _stream()))
+
+    def set(self, what: int, layer: int, src):
+        """Restore weights, bias or an Adam moment of `layer` (pg_mlp_set) from a float32 device tensor."""
+        import torch
+
+        din, dout = self.dims[layer], self.dims[layer + 1]
+        shape = (din, dout) if what in (MLP_W, MLP_MW, MLP_VW) else (dout,)
+        if tuple(src.shape) != shape or src.dtype != torch.float32 or not src.is_contiguous():
+            raise ValueError(f"src must be a contiguous float32 tensor of shape {shape}")
+        _check(lib().pg_mlp_set(self._h, int(what), int(layer), _ptr(src), _stream()))
+
+    @property
+    def step(self) -> int:
+        """Adam updates taken so far."""
+        v = c_int64()
+        _check(lib().pg_mlp_get_step(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    @step.setter
+    def step(self, value: int):
+        _check(lib().pg_mlp_set_step(self._h, int(value)))
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

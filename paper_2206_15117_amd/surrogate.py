@@ -11,7 +11,9 @@ every output of the network is of order one; pg_kernels_import multiplies the sc
 
 Training (fit): the teacher's kernels span a low-dimensional space (a few dozen directions per
 Mueller cell), so the head is trained in two stages.  A rank-r orthonormal basis B of the
-(scaled) kernels is taken from a first block of teacher calls (randomised SVD); the network is
+(scaled) kernels is taken from a first block of teacher calls (randomised SVD: a Gaussian range
+finder with power iterations, every large product in the library's float32 GEMM, orthonormalised
+by shifted Cholesky QR whose r x r Gram factors are the only host arithmetic); the network is
 trained with its output layer in basis coordinates (targets K B^T, r outputs), which is cheap
 enough for many epochs over every teacher kernel; the output layer is then folded with the basis,
 W_head = W_r B, b_head = b_r B, giving the network of the stated shape that emits kernels
@@ -122,10 +124,12 @@ def train(net, teacher, scale, steps: int, batch: int = 256, pool_calls: int = 3
     xs = torch.empty((pool_calls * per, n_features()), dtype=torch.float32, device="cuda")
     inv = torch.from_numpy(1.0 / scale).cuda()
 
+    inv_rows = inv.float().repeat(teacher.planes).contiguous()
+
     def fill(slot):
         rows = slice(slot * per, (slot + 1) * per)
         x = teacher.call(pool[rows])
-        pool[rows] *= inv.repeat(teacher.planes)[:, None]
+        pg.scale_rows(pool[rows], inv_rows)
         xs[rows] = torch.from_numpy(x).cuda()
 
     for slot in range(pool_calls):
@@ -170,6 +174,64 @@ def surrogate_kernels(net, setup, w_planes, nu: float, pa: float, scale, chunk_p
     return k
 
 
+def _orthonormalise(y, passes: int = 3):
+    """Orthonormal columns spanning the columns of y (device float32 [n][q]): shifted Cholesky QR
+    (a first pass with a small diagonal shift of the Gram matrix, then passes that restore
+    orthogonality to rounding).  The teacher's kernels have fewer significant directions than q, so
+    the float32 Gram matrix can be singular to rounding; a pass whose factorisation fails is
+    repeated with a larger shift (the directions it then damps are rounding noise).  Gram products
+    and the re-basing y R^-1 run in pg_gemm_f32; only the q x q Cholesky factor and its inverse are
+    formed on the host, in float64."""
+    import torch
+
+    q = y.shape[1]
+    for it in range(passes):
+        gram = pg.gemm_f32(y, y, transa=True).double().cpu().numpy()
+        gram = 0.5 * (gram + gram.T)
+        mean_diag = np.trace(gram) / q
+        shift = 1e-6 * mean_diag if it == 0 else 0.0
+        for _ in range(8):
+            try:
+                r = np.linalg.cholesky(gram + shift * np.eye(q)).T   # gram + shift = r^T r
+                break
+            except np.linalg.LinAlgError:
+                shift = max(100.0 * shift, 1e-7 * mean_diag)
+        else:
+            raise np.linalg.LinAlgError("Gram matrix not positive definite even with a shift")
+        rinv = torch.from_numpy(np.linalg.inv(r).astype(np.float32)).cuda()
+        y = pg.gemm_f32(y, rinv)
+    return y
+
+
+def row_basis(k, rank: int, oversample: int = 16, power_iters: int = 4, seed: int = 1):
+    """Orthonormal rows [rank][d] spanning the dominant row space of k [n][d] (device float32): a
+    randomised SVD (Halko, Martinsson and Tropp's range finder with power iterations) on k^T, every
+    large product in pg_gemm_f32.  The Gaussian test matrix is drawn by torch's generator and passed
+    in; the q x q eigenproblem of the projected matrix is solved on the host in float64."""
+    import torch
+
+    n, d = k.shape
+    q = min(rank + oversample, n)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    omega = torch.randn((n, q), dtype=torch.float32, device="cuda", generator=gen)
+    y = _orthonormalise(pg.gemm_f32(k, omega, transa=True))          # [d][q]: range of k^T
+    for _ in range(power_iters):
+        z = _orthonormalise(pg.gemm_f32(k, y))                        # [n][q]
+        y = _orthonormalise(pg.gemm_f32(k, z, transa=True))           # [d][q]
+    b = pg.gemm_f32(k, y)                                             # k y = u s w^T
+    gram = pg.gemm_f32(b, b, transa=True).double().cpu().numpy()      # w s^2 w^T
+    evals, w = np.linalg.eigh(0.5 * (gram + gram.T))
+    w_top = np.ascontiguousarray(w[:, np.argsort(evals)[::-1][:rank]].T.astype(np.float32))
+    return pg.gemm_f32(torch.from_numpy(w_top).cuda(), y, transb=True)  # [rank][d] = (y w)^T
+
+
+def _residual(k, c, basis) -> float:
+    """Mean relative squared residual |k - c basis|^2 / |k|^2 of rows projected onto the basis."""
+    r = pg.gemm_f32(c, basis, out=k.clone(), alpha=-1.0, beta=1.0)
+    return float((r.pow(2).sum(1) / k.pow(2).sum(1)).mean())
+
+
 def teacher_data(teacher, scale, calls: int, basis_calls: int = 64, rank: int = 256, seed: int = 1, log=None):
     """Teacher kernels of `calls` calls reduced to basis coordinates.
 
@@ -179,19 +241,17 @@ def teacher_data(teacher, scale, calls: int, basis_calls: int = 64, rank: int = 
     t_start = time.perf_counter()
     per = teacher.planes * N_CELLS
     d = teacher.cell_len
-    inv = torch.from_numpy(1.0 / scale).cuda().repeat(teacher.planes)[:, None]
+    inv = torch.from_numpy((1.0 / scale).astype(np.float32)).cuda().repeat(teacher.planes).contiguous()
     nb = min(basis_calls, calls)
     k0 = torch.empty((nb * per, d), dtype=torch.float32, device="cuda")
     feats = []
     for c in range(nb):
         rows = slice(c * per, (c + 1) * per)
         feats.append(teacher.call(k0[rows]))
-        k0[rows] *= inv
-    torch.manual_seed(seed)
-    _, _, v = torch.svd_lowrank(k0, q=min(rank + 16, k0.shape[0]), niter=4)
-    basis = v[:, :rank].T.contiguous()                      # [rank][d], orthonormal rows
-    coef = [k0 @ basis.T]
-    resid0 = float(((k0 - coef[0] @ basis).pow(2).sum(1) / k0.pow(2).sum(1)).mean())
+        pg.scale_rows(k0[rows], inv)
+    basis = row_basis(k0, rank, seed=seed)                   # [rank][d], orthonormal rows
+    coef = [pg.gemm_f32(k0, basis, transb=True)]
+    resid0 = _residual(k0[:512], coef[0][:512], basis)
     del k0
     torch.cuda.empty_cache()
     buf = torch.empty((per, d), dtype=torch.float32, device="cuda")
@@ -200,11 +260,11 @@ def teacher_data(teacher, scale, calls: int, basis_calls: int = 64, rank: int = 
         feats.append(teacher.call(buf))
         if log is not None and (c + 1) % 256 == 0:
             log(f"teacher call {c + 1}/{calls}")
-        buf *= inv
-        cc = buf @ basis.T
+        pg.scale_rows(buf, inv)
+        cc = pg.gemm_f32(buf, basis, transb=True)
         coef.append(cc)
         if c < nb + 8:
-            resid.append(float(((buf - cc @ basis).pow(2).sum(1) / buf.pow(2).sum(1)).mean()))
+            resid.append(_residual(buf, cc, basis))
     del buf
     x_all = torch.from_numpy(np.concatenate(feats)).cuda()
     c_all = torch.cat(coef)
@@ -247,7 +307,7 @@ def fold(net_r, basis, max_batch: int = 256, seed: int = 1):
     for layer in range(3):
         net.load(layer, net_r.copy(pg.MLP_W, layer), net_r.copy(pg.MLP_B, layer))
     w_r, b_r = net_r.copy(pg.MLP_W, 3), net_r.copy(pg.MLP_B, 3)
-    net.load(3, (w_r @ basis).contiguous(), (b_r[None] @ basis)[0].contiguous())
+    net.load(3, pg.gemm_f32(w_r.contiguous(), basis), pg.gemm_f32(b_r.view(1, -1).contiguous(), basis)[0])
     torch.cuda.synchronize()
     return net
 

@@ -149,21 +149,21 @@ def test_batch_rejects_mixed_npol(fields):
 
 def test_full_size_batched_fields_sampled():
     """The 16-field workload (4096^2 x 4 each, float16 tables, 16.1M rows) in the benchmark's launch
-    configuration: one grid launch over all fields with visibilities that are zero except
-    a seeded sample in the smallest and the largest field; those two grids against the oracle (its
-    tables rounded to float16), every other grid exactly zero; then one degrid launch,
-    sampled rows of the same two fields against the oracle."""
+    configuration: one grid launch over all fields with visibilities that are zero except a seeded
+    sample of every field (rows of its densest plane and of its first populated plane); every
+    field's grid against the oracle (its tables rounded to float16); then one degrid launch, the
+    sampled rows of every field against the oracle."""
     from oracle import geometry
+    from oracle_pool import tables_for_tasks
     from paper_2206_15117_amd import autotune
 
     pg.use_torch_allocator(True)
     ws = synth.config3()
     nf = len(ws)
     n = ws[0].geom.n
-    counts = [w.nvis for w in ws]
-    check = sorted({int(np.argmin(counts)), int(np.argmax(counts))})
+    check = list(range(nf))
     rng = np.random.default_rng(31)
-    fields, samples, tabs = [], {}, {}
+    fields, samples, tasks = [], {}, []
     for f, w in enumerate(ws):
         launch = autotune.apply(w.geom, 4, pg.STORE_F16)
         g = launch.geom
@@ -179,14 +179,17 @@ def test_full_size_batched_fields_sampled():
             cnt = np.bincount(loc["plane"][loc["keep"]], minlength=g.nplanes)
             planes = sorted({int(np.argmax(cnt)), int(np.flatnonzero(cnt)[0])})
             s = np.sort(np.concatenate([rng.choice(np.flatnonzero((loc["plane"] == q) & loc["keep"]),
-                                                   min(60, int(cnt[q])), replace=False) for q in planes]))
+                                                   min(30, int(cnt[q])), replace=False) for q in planes]))
             vis[s] = synth.random_vis(len(s), 4, rng)
             samples[f] = s
-            tabs[f] = (kernels.round_tables(kernels.make_tables(g, mueller.phi_grid(jones, 0.2), planes=planes),
-                                            np.float16),
-                       kernels.round_tables(kernels.make_tables(g, mueller.phi_degrid(jones), planes=planes),
-                                            np.float16))
+            pgrid, pdeg = mueller.phi_grid(jones, 0.2), mueller.phi_degrid(jones)
+            tasks += [(f, kind, q, (g, phi, q)) for kind, phi in ((0, pgrid), (1, pdeg)) for q in planes]
         fields.append(dict(w=w, kg=kg, kd=kd, pg_=pgr, pd=pdg, vis=torch.from_numpy(vis).cuda()))
+    got_tabs = tables_for_tasks([t[3] for t in tasks], "16 fields")
+    tabs = {f: ([None] * ws[f].geom.nplanes, [None] * ws[f].geom.nplanes) for f in check}
+    for (f, kind, q, _), t in zip(tasks, got_tabs):
+        tabs[f][kind][q] = t
+    tabs = {f: (kernels.round_tables(a, np.float16), kernels.round_tables(b, np.float16)) for f, (a, b) in tabs.items()}
     grids = torch.empty((nf, 4, n, n), dtype=torch.complex64, device="cuda")
     b = pg.batch([(f["pg_"], f["kg"], f["vis"], grids[i]) for i, f in enumerate(fields)])
     b.grid(fftshift=True)

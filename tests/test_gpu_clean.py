@@ -159,3 +159,34 @@ def test_cotton_schwab_full_polarisation_converges():
           "sky I", float(model0[0].sum()))
     assert all(b < a for a, b in zip(pk, pk[1:]))
     assert pk[0] > 5 * pk[4]
+    # the sources sit where the beam is close to one, so the regularised flux is the sky's
+    model_i, sky_i = float(res.model[0].sum()), float(model0[0].sum())
+    assert abs(model_i - sky_i) < 0.02 * sky_i, (model_i, sky_i)
+    # Q, U and V follow I in the components (fractions 0.05, -0.03, 0.005 of every source)
+    for q, frac in ((1, 0.05), (2, -0.03)):
+        assert abs(float(res.model[q].sum()) - frac * sky_i) < 0.2 * abs(frac) * sky_i, q
+
+
+def test_masked_peak_and_normalise_at():
+    """pg_masked_peak against numpy (largest |value| over the mask, lowest index on ties, empty
+    mask), pg_normalise_at against float32 division by the reference pixel (bit for bit)."""
+    rng = np.random.default_rng(31)
+    img = rng.standard_normal((300, 301)).astype(np.float32)
+    img[7, 9] = -9.5
+    img[200, 3] = 9.5   # same |value|, higher index: the first one wins
+    mask = (rng.random((300, 301)) < 0.7).astype(np.uint8)
+    mask[7, 9] = mask[200, 3] = 1
+    peak, idx = pg.masked_peak(torch.from_numpy(img).cuda(), torch.from_numpy(mask).cuda())
+    assert (peak, idx) == (9.5, 7 * 301 + 9)
+    mask[7, 9] = 0
+    a = np.abs(img) * mask
+    peak, idx = pg.masked_peak(torch.from_numpy(img).cuda(), torch.from_numpy(mask).cuda())
+    assert peak == float(a.max()) and idx == int(np.argmax(a))
+    assert pg.masked_peak(torch.from_numpy(img).cuda()) == (9.5, 7 * 301 + 9)
+    assert pg.masked_peak(torch.from_numpy(img).cuda(), torch.zeros((300, 301), dtype=torch.uint8).cuda()) == (0.0, -1)
+    x = torch.from_numpy(img).cuda()
+    pg.normalise_at(x, 150 * 301 + 150)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), img / img[150, 150])
+    with pytest.raises(pg.PolgridError):
+        pg.normalise_at(x, x.numel())

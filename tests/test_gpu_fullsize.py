@@ -4,8 +4,9 @@ length, waves per workgroup and XCD grouping, centring folded into grid/degrid):
   c5  major cycle 8192^2 x 4, 128 planes, supports 16-48, os 8, 20M rows (288 channels).
 
 The oracle cannot grid millions of rows in seconds, so: the plan is compared bit-exactly in full;
-grid and degrid are compared on a seeded sample of rows drawn from three planes (the densest
-plane, a mid plane and an S = 48 plane), with every other visibility set to zero for grid; the
+grid and degrid are compared on a seeded sample of rows drawn from every populated plane (c2: all
+31, so every (support, tile) launch shape the benchmark runs) or from the most populated plane of
+every support class (c5: 17 planes), with every other visibility set to zero for grid; the
 adjoint identity is checked over all rows.
 """
 import numpy as np
@@ -14,6 +15,7 @@ import pytest
 import synth
 from oracle import geometry, gridding, kernels, mueller
 from oracle import plan as oplan
+from oracle_pool import tables_in_parallel
 
 torch = pytest.importorskip("torch")
 pg = pytest.importorskip("paper_2206_15117_amd.polgrid")
@@ -42,19 +44,22 @@ def full(request):
     p = autotune.plan(kg, uvw, launch)
     loc = geometry.locate(g, w.uvw)
     counts = np.bincount(loc["plane"], minlength=g.nplanes)
-    dense = int(np.argmax(counts))
-    big = int(np.flatnonzero((g.support == g.support.max()) & (counts > 0))[0])
-    mid = int(np.flatnonzero((g.support > 24) & (g.support < 40) & (counts > 100))[0])
-    planes = sorted({dense, big, mid})
+    if request.param == "c2":
+        planes = [int(q) for q in np.flatnonzero(counts > 0)]
+        per = 40
+    else:
+        planes = sorted(int(max(np.flatnonzero(g.support == s), key=lambda q: counts[q]))
+                        for s in np.unique(g.support) if counts[g.support == s].sum() > 0)
+        per = 60
     rng = np.random.default_rng(2022)
-    sample = np.concatenate([rng.choice(np.flatnonzero(loc["plane"] == q), min(150, int(counts[q])), replace=False)
+    sample = np.concatenate([rng.choice(np.flatnonzero(loc["plane"] == q), min(per, int(counts[q])), replace=False)
                              for q in planes])
-    tg = kernels.make_tables(g, mueller.phi_grid(jones, w.eps_null), planes=planes)
-    td = kernels.make_tables(g, mueller.phi_degrid(jones), planes=planes)
+    tg = tables_in_parallel(g, mueller.phi_grid(jones, w.eps_null), planes, request.param + " grid")
+    td = tables_in_parallel(g, mueller.phi_degrid(jones), planes, request.param + " degrid")
     n = g.n
     sign = ((-1.0) ** (np.arange(n)[:, None] + np.arange(n)[None, :]))[None]
     return dict(w=w, kg=kg, kd=kd, uvw=uvw, p=p, sample=np.sort(sample), tg=tg, td=td, sign=sign,
-                chunk=launch.max_chunk)
+                chunk=launch.max_chunk, planes=planes)
 
 
 def test_full_plan_bit_exact(full):
@@ -69,6 +74,18 @@ def test_full_plan_bit_exact(full):
     it = want["items"]
     t = w.geom.tile[it[:, 0]]
     assert np.array_equal(items[:, :5], np.stack([it[:, 0], it[:, 1] * t, it[:, 2] * t, it[:, 3], it[:, 4]], 1))
+
+
+def test_full_sample_covers_every_launch_shape(full):
+    """The sampled planes cover every (support, tile) pair of the launch (c2) or every support (c5)."""
+    g, planes = full["w"].geom, full["planes"]
+    counts = np.bincount(geometry.locate(g, full["w"].uvw)["plane"], minlength=g.nplanes)
+    used = {(int(g.support[q]), int(g.tile[q])) for q in np.flatnonzero(counts > 0)}
+    got = {(int(g.support[q]), int(g.tile[q])) for q in planes}
+    if len(planes) >= np.count_nonzero(counts):
+        assert got == used
+    else:
+        assert {s for s, _ in got} == {s for s, _ in used}
 
 
 def test_full_grid_sampled_rows(full):

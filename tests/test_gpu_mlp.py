@@ -24,16 +24,18 @@ def test_forward_layer_by_layer():
     net = pg.MLP(20, 64, 2, 300, max_batch=64, seed=11)
     gen = torch.Generator(device="cuda").manual_seed(1)
     x = torch.randn((37, 20), device="cuda", generator=gen)  # ragged against the 64-row tiles
-    y = net.forward(x)
+    y = net.forward(x)   # the output layer writes y directly
     for l in range(3):
         a = f64(net.copy(pg.MLP_ACT, l, 37))
         w = f64(net.copy(pg.MLP_W_BF16, l))
         b = f64(net.copy(pg.MLP_B, l))
-        z = f64(net.copy(pg.MLP_PRE, l, 37))
+        z = f64(y) if l == 2 else f64(net.copy(pg.MLP_PRE, l, 37))
         assert rel(z, a @ w + b) < 1e-5, l
         if l < 2:  # next layer's input is SiLU of this pre-activation rounded to bfloat16
             nxt = f64(net.copy(pg.MLP_ACT, l + 1, 37))
             assert np.max(np.abs(nxt - omlp.silu(z))) <= 2 ** -8 * np.max(np.abs(omlp.silu(z))) + 1e-6
+    # a training step's own forward leaves the output in the network's buffer: the same bits
+    net.train_step(x, torch.zeros_like(y), lr=0.0, update=False)
     assert rel(f64(y), f64(net.copy(pg.MLP_PRE, 2, 37))) == 0.0
 
 

@@ -380,3 +380,51 @@ def test_single_visibility_reproduces_kernel_and_edges(c2_case):
         got = host(pg.grid(p, kg, dev(vis)))
         want = gridding.grid(g, tg, uvw, vis.astype(np.complex128))
         assert rel(got, want) < 1e-6 if loc["keep"][0] else np.all(got == 0)
+
+
+# ------------------------------------------------------------------ large supports at oracle size
+
+@pytest.fixture(scope="module")
+def big_case():
+    """Supports 34-48 with the benchmark's tiles for them (T = 1 for S >= 40, 2 for 36, 5 for 34),
+    on a 256^2 grid the oracle grids in seconds."""
+    w = synth.scaled_config2(4000, n=256, nplanes=6, mk=64, support=[48, 44, 40, 36, 34, 42],
+                             tile=[1, 1, 1, 2, 5, 1])
+    rng = np.random.default_rng(12)
+    vis = synth.random_vis(w.nvis, 4, rng)
+    tg = kernels.make_tables(w.geom, oracle_phi(w, pg.KIND_GRID))
+    td = kernels.make_tables(w.geom, oracle_phi(w, pg.KIND_DEGRID))
+    kg = gpu_kernels(w, pg.KIND_GRID)
+    kd = gpu_kernels(w, pg.KIND_DEGRID)
+    counts = np.bincount(geometry.locate(w.geom, w.uvw)["plane"], minlength=6)
+    assert np.count_nonzero(counts) >= 4, counts
+    return w, vis, tg, td, kg, kd
+
+
+@pytest.mark.parametrize("launch", [(2, 4, 8, 2, 1, 2), (0, 16, 16, 1, 0, 0), (1, 16, 16, 1, 0, 0), (2, 8, 4, 3, 2, 0)])
+def test_large_support_grid_and_degrid(big_case, launch):
+    """The benchmark's launch for these planes (row bands, 4 waves, one output plane per
+    workgroup, XCD groups of 2; degrid 8 waves with the correlation split) and other settings."""
+    w, vis, tg, td, kg, kd = big_case
+    p = pg.plan(kg, dev(w.uvw), max_chunk=256).set_launch(*launch)
+    got = host(pg.grid(p, kg, dev(vis), fftshift=True))
+    n = w.geom.n
+    sign = (-1.0) ** (np.arange(n)[:, None] + np.arange(n)[None, :])
+    want = gridding.grid(w.geom, tg, w.uvw, vis) * sign[None]
+    for q in range(4):
+        assert rel(got[q], want[q]) < TOL, q
+    rng = np.random.default_rng(13)
+    g = (rng.standard_normal((4, n, n)) + 1j * rng.standard_normal((4, n, n))).astype(np.complex64)
+    pd = pg.plan(kd, dev(w.uvw), max_chunk=256).set_launch(*launch)
+    got = host(pg.degrid(pd, kd, dev(g * sign[None].astype(np.float32)), fftshift=True))
+    want = gridding.degrid(w.geom, td, w.uvw, g)
+    for c in range(4):
+        assert rel(got[:, c], want[:, c]) < TOL, c
+
+
+def test_large_support_float16_tables(big_case):
+    w, vis, tg, _, _, _ = big_case
+    k16 = gpu_kernels(w, pg.KIND_GRID, storage=pg.STORE_F16)
+    p = pg.plan(k16, dev(w.uvw), max_chunk=256).set_launch(2, 8, 8, 16)
+    got = host(pg.grid(p, k16, dev(vis)))
+    assert rel(got, gridding.grid(w.geom, kernels.round_tables(tg, np.float16), w.uvw, vis)) < TOL
