@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--max-chunk", type=int, default=0, help="0: the tuned value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=450000)
-    ap.add_argument("--grid-variant", choices=["auto", "atomic", "banded"], default="auto")
+    ap.add_argument("--grid-variant", choices=["auto", "atomic", "banded", "shared"], default="auto")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-field section")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-kernel section")
     ap.add_argument("--no-scale", action="store_true", help="skip the 20M-row major-cycle section")
@@ -99,7 +99,8 @@ def main():
     if args.network_only:
         print(json.dumps({"network": bench_network()}), flush=True)
         return
-    variant = {"auto": 0, "atomic": pg.VARIANT_ATOMIC, "banded": pg.VARIANT_BANDED}[args.grid_variant]
+    variant = {"auto": 0, "atomic": pg.VARIANT_ATOMIC, "banded": pg.VARIANT_BANDED,
+               "shared": pg.VARIANT_SHARED}[args.grid_variant]
     from paper_2206_15117_amd import autotune
 
     w = synth.config2(nvis=args.nvis)
@@ -109,7 +110,7 @@ def main():
         launch = launch._replace(max_chunk=args.max_chunk)
     g, max_chunk, tuned_variant, gw, dw = launch[:5]
     if variant == 0:
-        variant = {1: pg.VARIANT_ATOMIC, 2: pg.VARIANT_BANDED}.get(tuned_variant, 0)
+        variant = {1: pg.VARIANT_ATOMIC, 2: pg.VARIANT_BANDED, 3: pg.VARIANT_SHARED}.get(tuned_variant, 0)
     jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
     uvw = torch.from_numpy(w.uvw).cuda()
 

@@ -76,15 +76,17 @@ extern "C" {
                                without either flag the library picks by sub-grid width.
                                Both give the same result up to float32 summation order. */
 #define PG_VARIANT_SHARED 32 /* pg_grid: force the shared-tap kernel: rows of one kernel phase share
-                                each tap load, and the sub-grid is summed in fixed point with LDS
-                                integer atomics (per item and plane, scaled from a bound on its
-                                values; inputs must be finite, an item with a non-finite
-                                visibility turns its grid points into NaN) */
+                                each tap load, and the sub-grid is summed exactly in two-word fixed
+                                point with LDS integer atomics (per item and plane, scaled from a
+                                bound on its values); an item with a non-finite visibility turns
+                                its grid points into NaN.  Needs twice one output plane's sub-grid
+                                in LDS; where that does not fit the row-band kernel runs instead */
 #define PG_DETERMINISTIC 16 /* pg_grid: bit-for-bit reproducible result.  Each work item's sub-grid
-                               is summed in a fixed order (row bands, 8 waves, all planes in one
-                               workgroup, whatever the plan's launch settings), and the sub-grids
-                               are added into 64-bit fixed-point accumulators with integer atomics,
-                               which do not depend on the order of the additions.  The fixed-point
+                               is summed exactly (the shared-tap kernel's fixed point, with a launch
+                               shape that depends only on the kernel set; where that does not fit
+                               the LDS, row bands in a fixed order), and the sub-grids are added
+                               into 64-bit fixed-point accumulators with integer atomics, which do
+                               not depend on the order of the additions.  The fixed-point
                                scale is a power of two chosen per call from a bound on every grid
                                value (rows kept x largest row |vis|_1 x largest |re|+|im| of a
                                table entry), so that no sum can overflow; inputs must be finite.

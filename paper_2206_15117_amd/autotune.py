@@ -6,7 +6,8 @@ Searches, per geometry class (npol, storage, os, per-plane supports):
   * waves per workgroup for grid and degrid (4, 6, 8, 16);
   * output planes per gridder workgroup (all, 2 or 1 of the four correlations), and output
     correlations per degridder workgroup (all or 2, float32 tables);
-  * the grid variant (row bands or LDS atomics) and the chunk length of work items;
+  * the grid variant (row bands, shared taps with fixed-point LDS accumulation, or LDS float
+    atomics) and the chunk length of work items;
   * how many consecutive work items share one XCD (and its L2), for the best shape found.
 Each candidate is timed with HIP events on a representative workload; the best choice is
 cached in tuning.json beside this file and read back by `tuned_config`.
@@ -159,7 +160,8 @@ def tune(geom, npol, jones, uvw, vis, eps_null=0.2, storage=0, reps=3, wgs=(1, 2
         for chunk in chunks:
             p = pg.plan(kg, uvw, max_chunk=chunk)
             for nw in waves:
-                for variant, gp in [(2, q) for q in planes if q == 0 or npol % q == 0] + [(1, 0)]:
+                cands = [(v, q) for v in (2, 3) for q in planes if q == 0 or npol % q == 0] + [(1, 0)]
+                for variant, gp in cands:
                     if variant == 1 and nw != 16:
                         continue
                     p.set_launch(variant, nw, nw, 1, gp)

@@ -499,18 +499,33 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_kernel(const Item* __rest
 // phase per pass, loading every tap once and applying it to all R rows, whose sub-grid positions
 // differ by wave-uniform offsets.  Waves overlap in the sub-grid, so it is accumulated with LDS
 // integer atomics (on CDNA4 these run at about the rate of plain LDS read-modify-write; float LDS
-// atomics are over an order of magnitude slower) in fixed point: output plane q of the item uses
-// the scale 2^e_q, B_q 2^e_q < 2^29, where B_q = kbound[plane][q] x the sum over the item's rows of
-// sum_c |Re V_c| + |Im V_c| bounds every sub-grid value of the plane and the sum of the magnitudes
-// of its terms, so no sum can overflow and one unit is at most B_q 2^-28: finer than float32
-// rounding of the terms it replaces.
-constexpr int kSharedScratch = 64;  // bytes after the sub-grid: the per-wave partial sums
+// atomics are over an order of magnitude slower), exactly, in two-word fixed point:
+//   * the item's scale 2^e puts B = max_q kbound[plane][q] x rows x the largest row sum
+//     sum_c |Re V_c| + |Im V_c| (a bound on every value of the sub-grid and on the sum of the
+//     magnitudes of its terms, independent of summation order) below 2^29; visibilities are
+//     multiplied by 2^e as they are read, so every term y comes out already scaled;
+//   * each term is split into h = round(y) and l = trunc((y - h) 2^f), f = min(20, 30 - log2 rows):
+//     coarse words sum to less than 2^30, fine words to less than 2^29, and the pair holds the sum
+//     of the float32 terms to 2^-(e + f), far below float32 rounding;
+//   * real and imaginary words are packed into one 64-bit integer, im 2^32 + re (re sign-extended),
+//     whose sums decode exactly while |sum re| < 2^31: one 64-bit LDS atomic per word pair.
+// The sub-grid of an item is therefore the same bits whatever the order of its additions.
+constexpr int kSharedScratch = 64;  // bytes after the sub-grid words: the per-wave maxima
+
+__device__ __forceinline__ unsigned long long pack_pair(int re, int im) {
+  return static_cast<unsigned long long>((static_cast<long long>(im) << 32) + static_cast<long long>(re));
+}
+__device__ __forceinline__ int2 unpack_pair(unsigned long long v) {
+  const int re = static_cast<int>(static_cast<unsigned>(v));
+  const int im = static_cast<int>(static_cast<long long>(v) >> 32) + (re < 0 ? 1 : 0);
+  return make_int2(re, im);
+}
 
 template <int NP, typename TapT, int R, int NQ>
-__device__ __forceinline__ void grid_rows_shared(int* lds, const TapT* __restrict__ pt, int j, int m_ly, int m_lx,
-                                                 int m_k, const float2* __restrict__ vis, int S, int SS, int P,
-                                                 int WP, float inv_s, const FootStep& step, int lane,
-                                                 const int (&ex)[NQ]) {
+__device__ __forceinline__ void grid_rows_shared(unsigned long long* lds, int fine_off, const TapT* __restrict__ pt,
+                                                 int j, int m_ly, int m_lx, int m_k, const float2* __restrict__ vis,
+                                                 int S, int SS, int P, int WP, float inv_s, const FootStep& step,
+                                                 int lane, int ex, float fscale) {
   const TapChunks<NQ * NP, TapT> tc(pt, SS);
   constexpr uint32_t TB = TapChunks<NQ * NP, TapT>::kTapBytes;
   const int ly0 = __builtin_amdgcn_readlane(m_ly, j), lx0 = __builtin_amdgcn_readlane(m_lx, j);
@@ -518,84 +533,108 @@ __device__ __forceinline__ void grid_rows_shared(int* lds, const TapT* __restric
   float2 v[R][NP];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    d[r] = 2 * ((__builtin_amdgcn_readlane(m_ly, j + r) - ly0) * P + __builtin_amdgcn_readlane(m_lx, j + r) - lx0);
+    d[r] = (__builtin_amdgcn_readlane(m_ly, j + r) - ly0) * P + __builtin_amdgcn_readlane(m_lx, j + r) - lx0;
     const int k = __builtin_amdgcn_readlane(m_k, j + r);
 #pragma unroll
-    for (int c = 0; c < NP; ++c) v[r][c] = vis[static_cast<size_t>(k) * NP + c];
+    for (int c = 0; c < NP; ++c) {
+      const float2 a = vis[static_cast<size_t>(k) * NP + c];
+      v[r][c] = make_float2(ldexpf(a.x, ex), ldexpf(a.y, ex));
+    }
   }
   TapCursor cur(lane, ly0, lx0, inv_s, S, P);
   uint32_t boff = static_cast<uint32_t>(lane) * TB;
   for (int t = lane; t < SS; t += 64) {
     float2 tap[NQ * NP];
     tc.load_at(boff, tap);
-    const int off = 2 * cur.off;
+    const int off = cur.off;
     boff += 64 * TB;
     cur.advance(step);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        float re = 0.0f, im = 0.0f;
+        float yr = 0.0f, yi = 0.0f;
 #pragma unroll
         for (int c = 0; c < NP; ++c) {
           const float2 a = tap[q * NP + c];
-          re = fmaf(a.x, v[r][c].x, fmaf(-a.y, v[r][c].y, re));
-          im = fmaf(a.x, v[r][c].y, fmaf(a.y, v[r][c].x, im));
+          yr = fmaf(a.x, v[r][c].x, fmaf(-a.y, v[r][c].y, yr));
+          yi = fmaf(a.x, v[r][c].y, fmaf(a.y, v[r][c].x, yi));
         }
-        int* cell = lds + 2 * q * WP + off + d[r];
-        atomicAdd(cell, __float2int_rn(ldexpf(re, ex[q])));
-        atomicAdd(cell + 1, __float2int_rn(ldexpf(im, ex[q])));
+        const float hr = rintf(yr), hi = rintf(yi);
+        unsigned long long* cell = lds + q * WP + off + d[r];
+        atomicAdd(cell, pack_pair(static_cast<int>(hr), static_cast<int>(hi)));
+        // fine words truncated toward zero: the residual left is below one fine unit
+        atomicAdd(cell + fine_off, pack_pair(static_cast<int>((yr - hr) * fscale), static_cast<int>((yi - hi) * fscale)));
       }
     }
   }
 }
 
-template <int NP, typename TapT, int NW, int NQ = NP>
+// FIXED: the reproducible mode's flush.  The item's values are exact integers at the scale
+// 2^(e + f); they are moved to the launch-wide scale of the 64-bit accumulators by a shift (exact
+// when it is a left shift, a floor when right) and added with integer atomics.
+template <int NP, typename TapT, int NW, int NQ = NP, bool FIXED = false>
 __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __restrict__ fine,
                                                  const int32_t* __restrict__ perm, const float2* __restrict__ vis,
                                                  const TapT* __restrict__ table, const PlaneInfo* __restrict__ planes,
                                                  const float* __restrict__ kbound, int os, int n,
                                                  float2* __restrict__ grid, int flags, int sub_bytes, float* lds_f,
-                                                 int q0 = 0) {
-  int* lds = reinterpret_cast<int*>(lds_f);  // [q][W][P][re, im] fixed point
+                                                 int q0 = 0, FixedSink fx = FixedSink{nullptr, nullptr}) {
+  // [coarse | fine][q][W][P] packed (re, im) words; sub_bytes covers both
+  unsigned long long* lds = reinterpret_cast<unsigned long long*>(lds_f);
   float* part = reinterpret_cast<float*>(reinterpret_cast<char*>(lds_f) + sub_bytes);  // [NW]
   const PlaneInfo pl = planes[it.plane];
   const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
+  const int fine_off = NQ * WP;
   const float inv_s = 1.0f / static_cast<float>(S);
-  for (int i = threadIdx.x; i < 2 * NQ * WP; i += NW * 64) lds[i] = 0;
-  // sum over the item's rows of sum_c |Re V_c| + |Im V_c|, the same float in every thread
-  float l1 = 0.0f;
+  for (int i = threadIdx.x; i < 2 * fine_off; i += NW * 64) lds[i] = 0ull;
+  // largest row sum of |Re V_c| + |Im V_c| over the item (a maximum: the same in every thread and
+  // for any partition of the rows)
+  float m1 = 0.0f;
   for (int i = it.start + static_cast<int>(threadIdx.x); i < it.end; i += NW * 64) {
     const size_t k = static_cast<size_t>(perm[i]);
+    float a1 = 0.0f;
 #pragma unroll
     for (int c = 0; c < NP; ++c) {
       const float2 a = vis[k * NP + c];
-      l1 += fabsf(a.x) + fabsf(a.y);
+      a1 += fabsf(a.x) + fabsf(a.y);
     }
+    m1 = (a1 > m1 || a1 != a1) ? a1 : m1;  // a NaN row wins, so a non-finite item is recognised
   }
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  l1 = wave_sum_to_lane63(l1);
-  if (lane == 63) part[wave] = l1;
-  __syncthreads();
-  float total = 0.0f;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) total += part[w];
-  int ex[NQ];
+  for (int o = 32; o >= 1; o >>= 1) {
+    const float other = __shfl_xor(m1, o, 64);
+    m1 = (other > m1 || other != other) ? other : m1;
+  }
+  if (lane == 0) part[wave] = m1;
+  __syncthreads();
+  float kmax = 0.0f;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) kmax = fmaxf(kmax, kbound[4 * it.plane + q0 + q]);
+  float mrow = 0.0f;
   bool finite = true;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const float b = kbound[4 * it.plane + q0 + q] * total;
-    int e2 = 0;
-    if (b > 0.0f && b <= 3.0e38f) {
-      frexpf(b, &e2);  // b < 2^e2
-      ex[q] = 29 - e2;
-    } else {
-      ex[q] = 0;
-      finite = finite && b == 0.0f;
-    }
+  for (int w = 0; w < NW; ++w) {
+    finite = finite && part[w] == part[w] && part[w] <= 3.0e38f;
+    mrow = fmaxf(mrow, part[w]);
   }
+  const int rows = it.end - it.start;
+  const float b = kmax * mrow * static_cast<float>(rows);
+  int ex = 0;
+  if (!(b <= 3.0e38f)) {
+    finite = false;
+  } else if (b > 0.0f) {
+    int e2 = 0;
+    frexpf(b, &e2);  // b < 2^e2
+    ex = 29 - e2;
+  }
+  int lg = 0;  // ceil(log2(rows))
+  while ((1 << lg) < rows && lg < 30) ++lg;
+  const int fbits = min(20, 30 - lg);
+  const float fscale = ldexpf(1.0f, fbits);
   const FootStep step(S, P);
-  const int per = (it.end - it.start + NW - 1) / NW;
+  const int per = (rows + NW - 1) / NW;
   const int w0 = it.start + wave * per, w1 = min(it.end, w0 + per);
   for (int blk = w0; blk < w1 && finite; blk += 64) {
     const int mine = blk + lane;
@@ -611,17 +650,24 @@ __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __re
     const int nrow = min(64, w1 - blk);
     for (int j = 0; j < nrow;) {
       const int ph = __builtin_amdgcn_readlane(m_ph, j);
-      int run = 1;  // rows from j on with the same phase, up to 4
-      while (run < 4 && j + run < nrow && __builtin_amdgcn_readlane(m_ph, j + run) == ph) ++run;
+      int run = 1;  // rows from j on with the same phase, up to 8
+      while (run < 8 && j + run < nrow && __builtin_amdgcn_readlane(m_ph, j + run) == ph) ++run;
       run = __builtin_amdgcn_readfirstlane(run);
       const TapT* pt = table + pl.offset + (static_cast<size_t>(ph) * NP * NP + q0 * NP) * SS;
-      if (run == 4) {
-        grid_rows_shared<NP, TapT, 4, NQ>(lds, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane, ex);
+      if (run == 8) {
+        grid_rows_shared<NP, TapT, 8, NQ>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
+                                          ex, fscale);
+      } else if (run >= 4) {
+        grid_rows_shared<NP, TapT, 4, NQ>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
+                                          ex, fscale);
+        run = 4;
       } else if (run >= 2) {
-        grid_rows_shared<NP, TapT, 2, NQ>(lds, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane, ex);
+        grid_rows_shared<NP, TapT, 2, NQ>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
+                                          ex, fscale);
         run = 2;
       } else {
-        grid_rows_shared<NP, TapT, 1, NQ>(lds, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane, ex);
+        grid_rows_shared<NP, TapT, 1, NQ>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
+                                          ex, fscale);
       }
       j += run;
     }
@@ -629,6 +675,37 @@ __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __re
   __syncthreads();
   const bool shift = (flags & PG_FFTSHIFT) != 0;
   const size_t pstride = static_cast<size_t>(n) * n;
+  if constexpr (FIXED) {
+    if (!finite) return;  // the reproducible mode requires finite inputs
+    const int sh = __builtin_amdgcn_readfirstlane(*fx.exp) - ex - fbits;
+    for (int idx = threadIdx.x; idx < W * W; idx += NW * 64) {
+      const int y = idx / W, x = idx - y * W;
+      const int X = it.ox + x, Y = it.oy + y;
+      if (X >= n || Y >= n) continue;
+      const int l = y * P + x;
+      const bool neg = shift && ((X + Y) & 1);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const unsigned long long cw = lds[q * WP + l], fw = lds[fine_off + q * WP + l];
+        if ((cw | fw) == 0ull) continue;
+        const int2 h = unpack_pair(cw), f = unpack_pair(fw);
+        long long v[2] = {static_cast<long long>(static_cast<unsigned long long>(static_cast<long long>(h.x)) << fbits) + f.x,
+                          static_cast<long long>(static_cast<unsigned long long>(static_cast<long long>(h.y)) << fbits) + f.y};
+        const size_t o = (q0 + q) * pstride + static_cast<size_t>(Y) * n + X;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          long long a = neg ? -v[c] : v[c];
+          if (sh >= 0) {
+            a = static_cast<long long>(static_cast<unsigned long long>(a) << min(sh, 63));
+          } else {
+            a = sh > -63 ? (a >> -sh) : (a < 0 ? -1 : 0);
+          }
+          atomicAdd(fx.acc + 2 * o + c, static_cast<unsigned long long>(a));
+        }
+      }
+    }
+    return;
+  }
   for (int idx = threadIdx.x; idx < W * W; idx += NW * 64) {
     const int y = idx / W, x = idx - y * W;
     const int X = it.ox + x, Y = it.oy + y;
@@ -643,10 +720,13 @@ __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __re
         unsafeAtomicAdd(gp + 1, __int_as_float(0x7fc00000));
         continue;
       }
-      const int a = lds[2 * (q * WP + l)], b = lds[2 * (q * WP + l) + 1];
-      if (a != 0 || b != 0) {
-        unsafeAtomicAdd(gp, sg * ldexpf(static_cast<float>(a), -ex[q]));
-        unsafeAtomicAdd(gp + 1, sg * ldexpf(static_cast<float>(b), -ex[q]));
+      const unsigned long long cw = lds[q * WP + l], fw = lds[fine_off + q * WP + l];
+      if ((cw | fw) != 0ull) {
+        const int2 h = unpack_pair(cw), f = unpack_pair(fw);
+        const double re = ldexp(static_cast<double>(h.x) + ldexp(static_cast<double>(f.x), -fbits), -ex);
+        const double im = ldexp(static_cast<double>(h.y) + ldexp(static_cast<double>(f.y), -fbits), -ex);
+        unsafeAtomicAdd(gp, sg * static_cast<float>(re));
+        unsafeAtomicAdd(gp + 1, sg * static_cast<float>(im));
       }
     }
   }
@@ -670,9 +750,27 @@ __global__ __launch_bounds__(NW * 64) void grid_shared_kernel(const Item* __rest
                                      sub_bytes, lds_f, part * NQ);
 }
 
-// Reproducible gridding: one workgroup of 8 waves per work item, all planes, row bands (a fixed
-// summation order inside the item whatever the plan's launch settings), flushed into the
-// fixed-point accumulators.
+// Reproducible gridding with the shared-tap kernel: 8 waves per workgroup and a number of output
+// planes per workgroup that depends only on the kernel set, so every item's exact sub-grid, and the
+// 64-bit sums of all items, are the same bits whatever the plan's launch settings.
+template <int NP, typename TapT, int NQ>
+__global__ __launch_bounds__(512) void grid_shared_fixed_kernel(const Item* __restrict__ items,
+                                                                const int2* __restrict__ fine,
+                                                                const int32_t* __restrict__ perm,
+                                                                const float2* __restrict__ vis,
+                                                                const TapT* __restrict__ table,
+                                                                const PlaneInfo* __restrict__ planes,
+                                                                const float* __restrict__ kbound, int os, int n,
+                                                                int flags, int sub_bytes, FixedSink fx) {
+  extern __shared__ float lds_f[];
+  const int item = blockIdx.x / (NP / NQ), part = blockIdx.x - item * (NP / NQ);
+  grid_item_shared<NP, TapT, 8, NQ, true>(items[item], fine, perm, vis, table, planes, kbound, os, n, nullptr, flags,
+                                          sub_bytes, lds_f, part * NQ, fx);
+}
+
+// Reproducible gridding where the shared-tap kernel does not fit: one workgroup of 8 waves per
+// work item, all planes, row bands (a fixed summation order inside the item whatever the plan's
+// launch settings), flushed into the fixed-point accumulators.
 template <int NP, typename TapT>
 __global__ __launch_bounds__(512) void grid_fixed_kernel(const Item* __restrict__ items, const int2* __restrict__ fine,
                                                          const int32_t* __restrict__ perm,
@@ -1027,7 +1125,7 @@ template <int NP, typename TapT, int NW, int NQ = NP>
 hipError_t run_grid_shared(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
                            hipStream_t s) {
   auto fn = grid_shared_kernel<NP, TapT, NW, NQ>;
-  const size_t sub = k->lds_bytes / NP * NQ;
+  const size_t sub = 2 * (k->lds_bytes / NP * NQ);  // coarse and fine words
   const size_t bytes = sub + kSharedScratch;
   hipError_t e = allow_lds(fn, bytes);
   if (e != hipSuccess) return e;
@@ -1038,12 +1136,16 @@ hipError_t run_grid_shared(const pg_plan* p, const pg_kernels* k, const float2* 
   return hipGetLastError();
 }
 
+// Output planes per workgroup: the plan's grid_planes (0: all), halved while the two-word sub-grid
+// would not fit the LDS.
 template <int NP, typename TapT, int NW>
 hipError_t run_grid_shared_planes(const pg_plan* p, const pg_kernels* k, const float2* vis, float2* grid, int flags,
                                   hipStream_t s) {
   if constexpr (NP == 4) {
-    if (p->grid_planes == 2) return run_grid_shared<NP, TapT, NW, 2>(p, k, vis, grid, flags, s);
-    if (p->grid_planes == 1) return run_grid_shared<NP, TapT, NW, 1>(p, k, vis, grid, flags, s);
+    int nq = (p->grid_planes == 1 || p->grid_planes == 2) ? p->grid_planes : 4;
+    while (nq > 1 && 2 * (k->lds_bytes / 4 * nq) + kSharedScratch > 163840) nq /= 2;
+    if (nq == 2) return run_grid_shared<NP, TapT, NW, 2>(p, k, vis, grid, flags, s);
+    if (nq == 1) return run_grid_shared<NP, TapT, NW, 1>(p, k, vis, grid, flags, s);
   }
   return run_grid_shared<NP, TapT, NW>(p, k, vis, grid, flags, s);
 }
@@ -1074,6 +1176,9 @@ hipError_t run_grid(const pg_plan* p, const pg_kernels* k, const float2* vis, fl
   if (flags & PG_VARIANT_ATOMIC) banded = false;
   if (flags & PG_VARIANT_BANDED) banded = true;
   if (flags & PG_VARIANT_SHARED) shared = true;
+  // the shared-tap kernel holds two words per value: one output plane of the widest sub-grid must
+  // fit twice, else the row-band kernel serves the launch
+  if (2 * (k->lds_bytes / NP) + kSharedScratch > 163840) shared = false;
   if (shared) {
     switch (p->grid_waves) {
       case 4: return run_grid_shared_planes<NP, TapT, 4>(p, k, vis, grid, flags, s);
@@ -1273,13 +1378,36 @@ hipError_t run_grid_fixed(const pg_plan* p, const pg_kernels* k, const float2* v
   hipLaunchKernelGGL(table_bound_kernel<TapT>, dim3(static_cast<unsigned>(std::min<int64_t>((entries + 255) / 256, 8192))),
                      dim3(256), 0, s, k->table.as<TapT>(), entries, bound + 1);
   hipLaunchKernelGGL(fixed_exponent_kernel, dim3(1), dim3(1), 0, s, bound, static_cast<double>(p->n_kept), exp);
-  auto fn = grid_fixed_kernel<NP, TapT>;
-  const size_t bytes = k->lds_bytes + kBandScratch;
-  e = allow_lds(fn, bytes);
+  int nq = NP;
+  while (nq > 1 && 2 * (k->lds_bytes / NP * nq) + kSharedScratch > 163840) nq /= 2;
+  const size_t sub = 2 * (k->lds_bytes / NP * nq);
+  if (sub + kSharedScratch <= 163840) {
+    auto launch = [&](auto fn) -> hipError_t {
+      hipError_t e2 = allow_lds(fn, sub + kSharedScratch);
+      if (e2 != hipSuccess) return e2;
+      hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items * (NP / nq))), dim3(512), sub + kSharedScratch, s,
+                         p->items.as<Item>(), p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(),
+                         k->planes.as<PlaneInfo>(), k->kbound.as<float>(), k->os, k->n, flags, static_cast<int>(sub),
+                         FixedSink{acc, exp});
+      return hipSuccess;
+    };
+    if constexpr (NP == 4) {
+      if (nq == 2) e = launch(grid_shared_fixed_kernel<NP, TapT, 2>);
+      else if (nq == 1) e = launch(grid_shared_fixed_kernel<NP, TapT, 1>);
+      else e = launch(grid_shared_fixed_kernel<NP, TapT, NP>);
+    } else {
+      e = launch(grid_shared_fixed_kernel<NP, TapT, NP>);
+    }
+  } else {
+    auto fn = grid_fixed_kernel<NP, TapT>;
+    const size_t bytes = k->lds_bytes + kBandScratch;
+    e = allow_lds(fn, bytes);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(512), bytes, s, p->items.as<Item>(),
+                         p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(), k->planes.as<PlaneInfo>(),
+                         k->os, k->n, flags, static_cast<int>(k->lds_bytes), FixedSink{acc, exp});
+  }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(p->n_items)), dim3(512), bytes, s, p->items.as<Item>(),
-                     p->fine.as<int2>(), p->perm.as<int32_t>(), vis, k->table.as<TapT>(), k->planes.as<PlaneInfo>(),
-                     k->os, k->n, flags, static_cast<int>(k->lds_bytes), FixedSink{acc, exp});
   hipLaunchKernelGGL(fixed_to_grid_kernel, dim3(static_cast<unsigned>(std::min<size_t>((count + 255) / 256, 16384))),
                      dim3(256), 0, s, acc, exp, count, grid, (flags & PG_ACCUMULATE) ? 1 : 0);
   return hipGetLastError();

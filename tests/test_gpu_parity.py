@@ -170,7 +170,7 @@ def test_c2_plan_bit_exact_with_drops(c2_case, max_chunk):
 
 # ------------------------------------------------------------------ A3 / A5: grid and degrid
 
-@pytest.mark.parametrize("variant", [0, pg.VARIANT_BANDED])
+@pytest.mark.parametrize("variant", [0, pg.VARIANT_BANDED, pg.VARIANT_SHARED])
 def test_c1_grid_parity(c1_case, variant):
     w, tabs, vis, k = c1_case
     p = pg.plan(k, dev(w.uvw), max_chunk=256)
@@ -189,8 +189,8 @@ def test_c1_degrid_parity(c1_case):
     assert rel(got, want) < TOL
 
 
-@pytest.mark.parametrize("variant", [pg.VARIANT_ATOMIC, pg.VARIANT_BANDED])
-@pytest.mark.parametrize("max_chunk", [64, 2048])
+@pytest.mark.parametrize("variant", [pg.VARIANT_ATOMIC, pg.VARIANT_BANDED, pg.VARIANT_SHARED])
+@pytest.mark.parametrize("max_chunk", [1, 64, 2048])
 def test_c2_grid_parity(c2_case, max_chunk, variant):
     w, vis, tg, _, kg, _ = c2_case
     p = pg.plan(kg, dev(w.uvw), max_chunk=max_chunk)
@@ -401,7 +401,8 @@ def big_case():
     return w, vis, tg, td, kg, kd
 
 
-@pytest.mark.parametrize("launch", [(2, 4, 8, 2, 1, 2), (0, 16, 16, 1, 0, 0), (1, 16, 16, 1, 0, 0), (2, 8, 4, 3, 2, 0)])
+@pytest.mark.parametrize("launch", [(2, 4, 8, 2, 1, 2), (0, 16, 16, 1, 0, 0), (1, 16, 16, 1, 0, 0), (2, 8, 4, 3, 2, 0),
+                                    (3, 4, 8, 2, 1, 2), (3, 8, 8, 1, 0, 0), (3, 16, 4, 5, 2, 0)])
 def test_large_support_grid_and_degrid(big_case, launch):
     """The benchmark's launch for these planes (row bands, 4 waves, one output plane per
     workgroup, XCD groups of 2; degrid 8 waves with the correlation split) and other settings."""
@@ -428,3 +429,69 @@ def test_large_support_float16_tables(big_case):
     p = pg.plan(k16, dev(w.uvw), max_chunk=256).set_launch(2, 8, 8, 16)
     got = host(pg.grid(p, k16, dev(vis)))
     assert rel(got, gridding.grid(w.geom, kernels.round_tables(tg, np.float16), w.uvw, vis)) < TOL
+
+
+@pytest.mark.parametrize("planes,waves,group", [(0, 4, 1), (1, 4, 2), (2, 8, 1), (0, 16, 64), (1, 6, 5)])
+def test_c2_shared_tap_gridder(c2_case, planes, waves, group):
+    """The shared-tap gridder (fixed-point LDS accumulation) at every waves-per-workgroup setting,
+    output-plane split and XCD grouping; float16 tables too."""
+    w, vis, tg, _, kg, _ = c2_case
+    p = pg.plan(kg, dev(w.uvw), max_chunk=100).set_launch(3, waves, waves, group, planes)
+    got = host(pg.grid(p, kg, dev(vis)))
+    want = gridding.grid(w.geom, tg, w.uvw, vis)
+    for q in range(4):
+        assert rel(got[q], want[q]) < TOL, (planes, q)
+    if waves == 4:
+        k16 = gpu_kernels(w, pg.KIND_GRID, storage=pg.STORE_F16)
+        p16 = pg.plan(k16, dev(w.uvw), max_chunk=100).set_launch(3, waves, waves, group, planes)
+        got = host(pg.grid(p16, k16, dev(vis)))
+        assert rel(got, gridding.grid(w.geom, kernels.round_tables(tg, np.float16), w.uvw, vis)) < TOL
+
+
+def test_shared_tap_gridder_on_faint_planes(c2_case):
+    """An unpolarised sky seen through the leaky beam: Q, U and V grids are leakage only, orders of
+    magnitude below I, and come from cancelling float32 Mueller products, so no float32 gridder
+    meets the 1e-5 bar on them alone.  The shared-tap gridder's fixed-point sums add no error of
+    their own: on every plane it is as close to the oracle as the row-band (float) gridder, and I
+    meets the bar."""
+    w, _, tg, _, kg, _ = c2_case
+    rng = np.random.default_rng(17)
+    i = rng.standard_normal(w.nvis) + 1j * rng.standard_normal(w.nvis)
+    vis = np.zeros((w.nvis, 4), np.complex64)
+    vis[:, 0] = i
+    vis[:, 3] = i
+    vis[:, 1] = 1e-3 * (rng.standard_normal(w.nvis) + 1j * rng.standard_normal(w.nvis))
+    want = gridding.grid(w.geom, tg, w.uvw, vis)
+    norms = [np.linalg.norm(want[q]) for q in range(4)]
+    assert min(norms[1:]) < 0.05 * norms[0]
+    err = {}
+    for variant in (pg.VARIANT_BANDED, pg.VARIANT_SHARED):
+        p = pg.plan(kg, dev(w.uvw), max_chunk=256)
+        got = host(pg.grid(p, kg, dev(vis), variant=variant))
+        err[variant] = [rel(got[q], want[q]) for q in range(4)]
+    print("per-plane error, row bands", err[pg.VARIANT_BANDED], "shared taps", err[pg.VARIANT_SHARED])
+    assert err[pg.VARIANT_SHARED][0] < TOL
+    for q in range(4):
+        assert err[pg.VARIANT_SHARED][q] <= 1.5 * err[pg.VARIANT_BANDED][q] + 1e-7, q
+
+
+def test_shared_tap_gridder_non_finite_and_rewritten_tables(c2_case):
+    """A NaN visibility makes its item's grid points NaN (and no others); after a table cell is
+    rewritten the per-plane bound follows it, so the gridder stays exact."""
+    w, vis, tg, _, _, _ = c2_case
+    k = gpu_kernels(w, pg.KIND_GRID)
+    p = pg.plan(k, dev(w.uvw), max_chunk=256)
+    bad = vis.copy()
+    bad[5, 2] = np.nan
+    got = host(pg.grid(p, k, dev(bad), variant=pg.VARIANT_SHARED))
+    assert np.isnan(got).any() and np.isfinite(got).mean() > 0.9
+    # scale one plane's cells up by 1e6: the fixed-point bound must follow the table
+    plane = int(np.bincount(geometry.locate(w.geom, w.uvw)["plane"], minlength=w.geom.nplanes).argmax())
+    cells = k.export_planes(plane, 1) * 1e6
+    k.import_planes(plane, 1, cells.contiguous())
+    t2 = list(tg)
+    t2[plane] = kernels.round_tables([tg[plane]], np.complex64)[0] * 1e6
+    got = host(pg.grid(pg.plan(k, dev(w.uvw), max_chunk=256), k, dev(vis), variant=pg.VARIANT_SHARED))
+    want = gridding.grid(w.geom, t2, w.uvw, vis)
+    for q in range(4):
+        assert rel(got[q], want[q]) < TOL, q
