@@ -119,9 +119,9 @@ def plan(kernels, uvw, launch: Launch):
     """A plan binned for `kernels` with the tuned chunk length and launch shape."""
     from . import polgrid as pg
 
-    return pg.plan(kernels, uvw, max_chunk=launch.max_chunk).set_launch(0, launch.grid_waves, launch.degrid_waves,
-                                                                        launch.xcd_group, launch.grid_planes,
-                                                                        launch.degrid_corrs)
+    return pg.plan(kernels, uvw, max_chunk=launch.max_chunk).set_launch(launch.variant, launch.grid_waves,
+                                                                        launch.degrid_waves, launch.xcd_group,
+                                                                        launch.grid_planes, launch.degrid_corrs)
 
 
 def _time(fn, reps):

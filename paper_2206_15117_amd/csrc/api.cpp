@@ -451,6 +451,8 @@ int pg_batch_create(const pg_field* fields, int32_t nfields, void* stream, pg_ba
         b->storage = fd.kernels->storage;
         b->grid_waves = fd.plan->grid_waves;
         b->degrid_waves = fd.plan->degrid_waves;
+        b->grid_variant = fd.plan->grid_variant;
+        b->grid_planes = fd.plan->grid_planes;
       } else if (fd.kernels->npol != b->npol || fd.kernels->storage != b->storage) {
         return fail(PG_EINVAL, "all fields of a batch must share npol and table storage");
       }
@@ -461,7 +463,8 @@ int pg_batch_create(const pg_field* fields, int32_t nfields, void* stream, pg_ba
       b->lds_bytes = std::max(b->lds_bytes, fd.kernels->lds_bytes);
       fa[f] = FieldArgs{fd.plan->items.as<Item>(), fd.plan->fine.as<int2>(), fd.plan->perm.as<int32_t>(),
                         static_cast<float2*>(fd.vis), fd.kernels->table.p, fd.kernels->planes.as<PlaneInfo>(),
-                        static_cast<float2*>(fd.grid), fd.kernels->os, fd.kernels->n};
+                        static_cast<float2*>(fd.grid), fd.kernels->kbound.as<float>(), fd.kernels->os,
+                        fd.kernels->n};
       std::vector<Item> items(fd.plan->n_items);
       if (fd.plan->n_items) {
         PG_HIP(hipMemcpyAsync(items.data(), fd.plan->items.p, sizeof(Item) * items.size(), hipMemcpyDeviceToHost, s),

@@ -49,6 +49,7 @@ struct FieldArgs {
   const void* table;  // float2 or __half2 entries
   const PlaneInfo* planes;
   float2* grid;       // grid: output, degrid: input
+  const float* kbound;  // per-plane Mueller-row table bounds (shared-tap gridder)
   int32_t os, n;
 };
 
@@ -155,6 +156,8 @@ struct pg_batch {
   int64_t n_blocks = 0;  // launch size: n_work plus no-op entries that even out the XCD queues
   size_t lds_bytes = 0;          // largest sub-grid over the fields
   int32_t grid_waves = 16, degrid_waves = 16;
+  int32_t grid_variant = 0;  // 3: shared-tap gridder (from the first field's plan), else row bands
+  int32_t grid_planes = 0;   // output planes per shared-tap workgroup (from the first field's plan)
   std::vector<const pg_plan*> plans;
   std::vector<const pg_kernels*> kernels;
   std::vector<void*> vis, grids;

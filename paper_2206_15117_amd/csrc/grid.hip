@@ -907,10 +907,27 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_batch(const FieldArgs* __
                                             flags, sub_bytes, lds_f);
 }
 
+// The shared-tap gridder over a batch: workgroup b takes part b mod (NP / NQ) (its NQ output
+// planes) of the (field, item) pair work[b / (NP / NQ)].
+template <int NP, typename TapT, int NW, int NQ>
+__global__ __launch_bounds__(NW * 64) void grid_shared_batch(const FieldArgs* __restrict__ fields,
+                                                             const int2* __restrict__ work, int flags,
+                                                             int sub_bytes) {
+  extern __shared__ float lds_f[];
+  const int2 wr = work[blockIdx.x / (NP / NQ)];
+  if (wr.x < 0) return;
+  const int part = blockIdx.x % (NP / NQ);
+  ConstFieldArgs& fa = ((ConstFieldArgs*)fields)[wr.x];
+  grid_item_shared<NP, TapT, NW, NQ>(fa.items[wr.y], fa.fine, fa.perm, fa.vis, static_cast<const TapT*>(fa.table),
+                                     fa.planes, fa.kbound, fa.os, fa.n, fa.grid, flags, sub_bytes, lds_f, part * NQ);
+}
+
 // R consecutive rows of a work item that share one kernel phase (rows are phase-sorted inside a
 // tile), degridded together: every tap is loaded once and applied to all R rows, whose sub-grid
 // positions differ by a wave-uniform offset.  One 64-lane sum per row and output value; lane 63
 // writes the rows' visibilities.
+constexpr int kDegridRun = 8;  // longest run of same-phase rows whose tap loads one degrid pass shares
+
 template <int NP, typename TapT, int R, int NC = NP>
 __device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase_table, int j, int m_ly, int m_lx,
                                             int m_k, int S, int SS, int P, int WP, float inv_s,
@@ -1016,11 +1033,15 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
     const int nrow = min(64, w1 - blk);
     for (int j = 0; j < nrow;) {
       const int ph = __builtin_amdgcn_readlane(m_ph, j);
-      int run = 1;  // rows from j on with the same phase, up to 4
-      while (run < 4 && j + run < nrow && __builtin_amdgcn_readlane(m_ph, j + run) == ph) ++run;
+      int run = 1;  // rows from j on with the same phase, up to kDegridRun
+      while (run < kDegridRun && j + run < nrow && __builtin_amdgcn_readlane(m_ph, j + run) == ph) ++run;
       run = __builtin_amdgcn_readfirstlane(run);
       const TapT* pt = table + pl.offset + static_cast<size_t>(ph) * SS * NP * NP;
-      if (run == 4) {
+      if (kDegridRun >= 8 && run == 8) {
+        degrid_rows<NP, TapT, 8, NC>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane,
+                                    c0);
+      } else if (run >= 4) {
+        run = 4;
         degrid_rows<NP, TapT, 4, NC>(lds, pt, j, m_ly, m_lx, m_k, S, SS, P, WP, inv_s, step, vis_out, flags, lane,
                                     c0);
       } else if (run >= 2) {
@@ -1244,8 +1265,32 @@ hipError_t run_degrid(const pg_plan* p, const pg_kernels* k, const float2* grid,
   }
 }
 
+template <int NP, typename TapT, int NW, int NQ>
+hipError_t run_batch_grid_shared(const pg_batch* b, int flags, hipStream_t s) {
+  auto fn = grid_shared_batch<NP, TapT, NW, NQ>;
+  const size_t sub = 2 * (b->lds_bytes / NP * NQ);
+  const size_t bytes = sub + kSharedScratch;
+  hipError_t e = allow_lds(fn, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(b->n_blocks * (NP / NQ))), dim3(NW * 64), bytes, s,
+                     b->fields.as<FieldArgs>(), b->work.as<int2>(), flags, static_cast<int>(sub));
+  return hipGetLastError();
+}
+
 template <int NP, typename TapT, int NW>
 hipError_t run_batch_grid(const pg_batch* b, int flags, hipStream_t s) {
+  if (b->grid_variant == 3 && 2 * (b->lds_bytes / NP) + kSharedScratch <= 163840) {
+    // the first field's output planes per workgroup, halved while they do not fit twice in the LDS
+    if constexpr (NP == 4) {
+      int nq = (b->grid_planes == 1 || b->grid_planes == 2) ? b->grid_planes : 4;
+      while (nq > 1 && 2 * (b->lds_bytes / 4 * nq) + kSharedScratch > 163840) nq /= 2;
+      if (nq == 4) return run_batch_grid_shared<NP, TapT, NW, 4>(b, flags, s);
+      if (nq == 2) return run_batch_grid_shared<NP, TapT, NW, 2>(b, flags, s);
+      return run_batch_grid_shared<NP, TapT, NW, 1>(b, flags, s);
+    } else {
+      return run_batch_grid_shared<NP, TapT, NW, NP>(b, flags, s);
+    }
+  }
   auto fn = grid_banded_batch<NP, TapT, NW>;
   const size_t bytes = b->lds_bytes + kBandScratch;
   hipError_t e = allow_lds(fn, bytes);

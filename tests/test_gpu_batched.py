@@ -67,6 +67,25 @@ def test_batched_grid_and_degrid_match_oracle(storage, fields):
         assert rel(o.cpu().numpy(), want) < TOL
 
 
+@pytest.mark.parametrize("storage,planes,waves", [(pg.STORE_F32, 1, 8), (pg.STORE_F32, 0, 4), (pg.STORE_F16, 2, 16)])
+def test_batched_shared_tap_gridder(storage, planes, waves):
+    """The shared-tap gridder over a batch (the first field's plan selects it, with its output
+    planes per workgroup and waves) against the oracle per field, and against single launches."""
+    fs = _fields(storage)
+    fs[0]["pg_"].set_launch(3, waves, waves, 1, planes)
+    vis = [torch.from_numpy(f["vis"]).cuda() for f in fs]
+    grids = [torch.empty((4, f["w"].geom.n, f["w"].geom.n), dtype=torch.complex64, device="cuda") for f in fs]
+    b = pg.batch([(f["pg_"], f["kg"], v, g) for f, v, g in zip(fs, vis, grids)])
+    b.grid(fftshift=True)
+    n_sign = [(-1.0) ** (np.arange(f["w"].geom.n)[:, None] + np.arange(f["w"].geom.n)[None, :]) for f in fs]
+    for f, v, g, sg in zip(fs, vis, grids, n_sign):
+        want = gridding.grid(f["w"].geom, f["tg"], f["w"].uvw, f["vis"]) * sg[None]
+        for q in range(4):
+            assert rel(g.cpu().numpy()[q], want[q]) < TOL, q
+        one = pg.grid(f["pg_"], f["kg"], v, fftshift=True, variant=pg.VARIANT_SHARED)
+        assert rel(g.cpu().numpy(), one.cpu().numpy()) < 1e-6
+
+
 def test_batched_equals_single_field_launches(fields):
     vis = [torch.from_numpy(f["vis"]).cuda() for f in fields]
     grids = [torch.empty((4, f["w"].geom.n, f["w"].geom.n), dtype=torch.complex64, device="cuda") for f in fields]

@@ -122,3 +122,17 @@ def test_full_adjoint_identity(full):
     rhs = torch.vdot(x.to(torch.complex128).flatten(), gv.flatten()).item()
     scale = dx.norm().item() * v.to(torch.complex128).norm().item()
     assert abs(lhs - rhs) <= TOL * scale
+
+
+def test_full_shared_taps_match_row_bands_on_all_rows(full):
+    """Every row carrying data, at full size: the tuned kernel (shared taps, exact fixed-point
+    sub-grids, items up to the tuned chunk length) against the row-band float kernel, which the
+    sampled tests above tie to the oracle."""
+    w = full["w"]
+    vis = torch.from_numpy(synth.random_vis(w.nvis, 4, np.random.default_rng(21))).cuda()
+    a = pg.grid(full["p"], full["kg"], vis, variant=pg.VARIANT_SHARED)
+    b = pg.grid(full["p"], full["kg"], vis, variant=pg.VARIANT_BANDED)
+    torch.cuda.synchronize()
+    for q in range(4):
+        d = float((a[q] - b[q]).abs().norm() / b[q].abs().norm())
+        assert d < 1e-6, (q, d)
