@@ -108,7 +108,7 @@ def batch_plans(kernels_grid, kernels_degrid, uvw, launch: Launch):
 
     pg_ = pg.plan(kernels_grid, uvw, max_chunk=launch.max_chunk)
     pd_ = pg.plan(kernels_degrid, uvw, max_chunk=launch.max_chunk)
-    pg_.set_launch(0, launch.batch_grid_waves, launch.degrid_waves, launch.xcd_group, launch.grid_planes,
+    pg_.set_launch(launch.variant, launch.batch_grid_waves, launch.degrid_waves, launch.xcd_group, launch.grid_planes,
                    launch.degrid_corrs)
     pd_.set_launch(0, launch.grid_waves, launch.batch_degrid_waves, launch.xcd_group, launch.grid_planes,
                    launch.degrid_corrs)

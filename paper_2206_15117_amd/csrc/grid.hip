@@ -825,29 +825,6 @@ __global__ void table_bound_kernel(const TapT* __restrict__ table, int64_t count
   wave_max_to(out, m);
 }
 
-// kbound[4 p + q] = max over the entries of Mueller row q in plane p's table of |re| + |im|.
-// Entry i of a plane: e = i mod E, tap = (i / E) mod SS, chunk = (i / (E SS)) mod (npol^2 / E);
-// Mueller cell q npol + c = chunk E + e.
-template <typename TapT>
-__global__ void kernel_bound_kernel(const TapT* __restrict__ plane_table, int64_t count, int ss, int e_per_chunk,
-                                    int npol, unsigned* __restrict__ out) {
-  float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  const int nch = npol * npol / e_per_chunk;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int e = static_cast<int>(i % e_per_chunk);
-    const int chunk = static_cast<int>((i / e_per_chunk / ss) % nch);
-    const int q = (chunk * e_per_chunk + e) / npol;
-    const float2 t = tap_value(plane_table[i]);
-    const float a = fabsf(t.x) + fabsf(t.y);
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq)
-      if (qq == q) m[qq] = fmaxf(m[qq], a);
-  }
-#pragma unroll
-  for (int qq = 0; qq < 4; ++qq) wave_max_to(out + qq, m[qq]);
-}
-
 // Binary exponent e with n_kept bound[0] bound[1] 2^e < 2^61: two bits of headroom below the int64
 // range for the float rounding inside the sub-grid sums.  Zero when the bound is zero.
 __global__ void fixed_exponent_kernel(const unsigned* __restrict__ bound, double n_kept, int* __restrict__ exp) {
@@ -1378,29 +1355,6 @@ hipError_t launch_grid(const pg_plan* p, const pg_kernels* k, const float2* vis,
   const bool f16 = k->storage == PG_STORE_F16;
   if (k->npol == 4) return f16 ? run_grid<4, __half2>(p, k, vis, grid, flags, s) : run_grid<4, float2>(p, k, vis, grid, flags, s);
   return f16 ? run_grid<1, __half2>(p, k, vis, grid, flags, s) : run_grid<1, float2>(p, k, vis, grid, flags, s);
-}
-
-hipError_t refresh_kernel_bound(pg_kernels* k, int plane0, int nplanes, hipStream_t s) {
-  if (nplanes <= 0) return hipSuccess;
-  hipError_t e = launch_fill_zero(k->kbound.as<float>() + 4 * plane0, sizeof(float) * 4 * nplanes, s);
-  if (e != hipSuccess) return e;
-  const int nqc = k->npol * k->npol;
-  const int ec = chunk_entries(k->storage, nqc);
-  for (int p = plane0; p < plane0 + nplanes; ++p) {
-    const int64_t count = k->plane_offset[p + 1] - k->plane_offset[p];
-    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((count + 255) / 256, 2048));
-    unsigned* out = reinterpret_cast<unsigned*>(k->kbound.as<float>() + 4 * p);
-    const int ss = k->support[p] * k->support[p];
-    if (k->storage == PG_STORE_F16)
-      hipLaunchKernelGGL(kernel_bound_kernel<__half2>, dim3(blocks), dim3(256), 0, s,
-                         k->table.as<__half2>() + k->plane_offset[p], count, ss, ec, k->npol, out);
-    else
-      hipLaunchKernelGGL(kernel_bound_kernel<float2>, dim3(blocks), dim3(256), 0, s,
-                         k->table.as<float2>() + k->plane_offset[p], count, ss, ec, k->npol, out);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 size_t grid_fixed_scratch_bytes(const pg_kernels* k) {

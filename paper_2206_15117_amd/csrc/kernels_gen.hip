@@ -186,6 +186,37 @@ __global__ void cell_io_kernel(void* __restrict__ table, int storage, int nqc, i
   }
 }
 
+// kbound[4 p + q] = max over the entries of Mueller row q in plane p's table of |re| + |im|, the
+// bound the shared-tap gridder scales its fixed point from.  Block b takes phase b / nch, chunk
+// b mod nch of the plane: entries [b ss E, (b + 1) ss E), entry i of it is tap i / E, Mueller cell
+// chunk E + i mod E.  Per-thread maxima per row q, then a wave maximum and one integer atomic max
+// on the float bits per wave (non-negative floats order like their bits).
+__device__ inline float2 entry_value(float2 t) { return t; }
+__device__ inline float2 entry_value(__half2 t) { return __half22float2(t); }
+
+template <typename TapT>
+__global__ __launch_bounds__(256) void kernel_bound_kernel(const TapT* __restrict__ plane_table, int ss, int e_per_chunk,
+                                                           int nch, int npol, unsigned* __restrict__ out) {
+  const int chunk = static_cast<int>(blockIdx.x % static_cast<unsigned>(nch));
+  const TapT* blk = plane_table + static_cast<size_t>(blockIdx.x) * ss * e_per_chunk;
+  float m[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int i = threadIdx.x; i < ss * e_per_chunk; i += 256) {
+    const int q = (chunk * e_per_chunk + (i & (e_per_chunk - 1))) / npol;
+    const float2 t = entry_value(blk[i]);
+    const float a = fabsf(t.x) + fabsf(t.y);
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+      if (qq == q) m[qq] = fmaxf(m[qq], a);
+  }
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    float v = m[qq];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    if ((threadIdx.x & 63) == 0 && v > 0.0f) atomicMax(out + qq, __float_as_uint(v));
+  }
+}
+
 }  // namespace
 
 hipError_t cell_io(void* table, int storage, int nqc, int ce, int os, int support, int64_t offset0, int nplanes,
@@ -223,6 +254,28 @@ hipError_t launch_zgemm_nn(int batch, int m, int n, int k, const double2* a, int
   dim3 grid((n + BN - 1) / BN, (m + BM - 1) / BM, batch);
   hipLaunchKernelGGL(zgemm_kernel<false>, grid, dim3(256), 0, s, m, n, k, a, stride_a, b, stride_b, c, stride_c);
   return hipGetLastError();
+}
+
+hipError_t refresh_kernel_bound(pg_kernels* k, int plane0, int nplanes, hipStream_t s) {
+  if (nplanes <= 0) return hipSuccess;
+  hipError_t e = launch_fill_zero(k->kbound.as<float>() + 4 * plane0, sizeof(float) * 4 * nplanes, s);
+  if (e != hipSuccess) return e;
+  const int nqc = k->npol * k->npol;
+  const int ec = chunk_entries(k->storage, nqc), nch = nqc / ec;
+  for (int p = plane0; p < plane0 + nplanes; ++p) {
+    const unsigned blocks = static_cast<unsigned>(k->os * k->os * nch);
+    unsigned* out = reinterpret_cast<unsigned*>(k->kbound.as<float>() + 4 * p);
+    const int ss = k->support[p] * k->support[p];
+    if (k->storage == PG_STORE_F16)
+      hipLaunchKernelGGL(kernel_bound_kernel<__half2>, dim3(blocks), dim3(256), 0, s,
+                         k->table.as<__half2>() + k->plane_offset[p], ss, ec, nch, k->npol, out);
+    else
+      hipLaunchKernelGGL(kernel_bound_kernel<float2>, dim3(blocks), dim3(256), 0, s,
+                         k->table.as<float2>() + k->plane_offset[p], ss, ec, nch, k->npol, out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_pack(const double2* t, int support, int os, int nqc, int storage, void* table, hipStream_t s) {
