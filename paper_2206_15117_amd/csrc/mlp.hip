@@ -39,6 +39,7 @@ __device__ inline float bf2f(uint16_t h) { return __uint_as_float(static_cast<ui
 // with bias and optionally SiLU in bf16) is a template parameter.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128, BN = 128, BK = 32, LP = BK + 8;
 enum GemmEpi { kEpiStore, kEpiAccumulate, kEpiAtomic, kEpiBias, kEpiBiasSilu };
@@ -161,6 +162,39 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
   }
   // accumulator r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32 of a 32 x 32 tile
   const bool inside = m0 + BM <= M && n0 + BN <= N;
+  if constexpr (EPI == kEpiStore || EPI == kEpiBias) {
+    // Whole tiles of a 16-byte aligned output: each wave stages one 32 x 32 block at a time in
+    // its own 4 KiB of the (now idle) operand LDS and writes it back as rows of 16-byte streaming
+    // stores, 8 lanes per 128-byte row: a quarter of the store instructions of the per-element
+    // path below.  The final barrier of the k loop has retired every operand read.
+    if (inside && (ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0) {
+      float* stage = reinterpret_cast<float*>(&as[0][0]) + wave * 1024;  // [32][32]
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) stage[(8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * 32 + (lane & 31)] = acc[i][j][r];
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const int c4 = (lane & 7) * 4;
+          const int col = n0 + wn + j * 32 + c4;
+          f32x4 bv = {0.0f, 0.0f, 0.0f, 0.0f};
+          if constexpr (EPI == kEpiBias) bv = *reinterpret_cast<const f32x4*>(bias + col);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int rr = (lane >> 3) + 8 * k;
+            const f32x4 v = *reinterpret_cast<const f32x4*>(stage + rr * 32 + c4) + bv;
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(C + static_cast<int64_t>(m0 + wm + i * 32 + rr) * ldc + col));
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      return;
+    }
+  }
   float bj[2] = {0.0f, 0.0f};
   if constexpr (EPI == kEpiBias || EPI == kEpiBiasSilu) {
 #pragma unroll
@@ -185,7 +219,10 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
           } else {
             if constexpr (EPI == kEpiAccumulate) v += *c;
             if constexpr (EPI == kEpiBias || EPI == kEpiBiasSilu) v += bj[j];
-            *c = v;
+            if constexpr (EPI == kEpiBias || EPI == kEpiStore)
+              __builtin_nontemporal_store(v, c);  // streamed output: keep L2 for the weight tiles
+            else
+              *c = v;
             if constexpr (EPI == kEpiBiasSilu)
               act[static_cast<int64_t>(row) * ldc + col] = f2bf(__fdividef(v, 1.0f + __expf(-v)));
           }
