@@ -82,9 +82,10 @@ extern "C" {
                                 its grid points into NaN.  Needs twice one output plane's sub-grid
                                 in LDS; where that does not fit the row-band kernel runs instead */
 #define PG_DETERMINISTIC 16 /* pg_grid: bit-for-bit reproducible result.  Each work item's sub-grid
-                               is summed exactly (the shared-tap kernel's fixed point, with a launch
-                               shape that depends only on the kernel set; where that does not fit
-                               the LDS, row bands in a fixed order), and the sub-grids are added
+                               is summed exactly (the shared-tap kernel's fixed point, 8 waves and
+                               one output plane per workgroup whatever the plan's launch settings;
+                               where that does not fit the LDS, row bands in a fixed order), and
+                               the sub-grids are added
                                into 64-bit fixed-point accumulators with integer atomics, which do
                                not depend on the order of the additions.  The fixed-point
                                scale is a power of two chosen per call from a bound on every grid

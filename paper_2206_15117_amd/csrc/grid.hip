@@ -620,13 +620,14 @@ __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __re
     mrow = fmaxf(mrow, part[w]);
   }
   const int rows = it.end - it.start;
-  const float b = kmax * mrow * static_cast<float>(rows);
+  // in float64, so that only non-finite inputs (not a bound beyond the float range) stop the item
+  const double b = static_cast<double>(kmax) * static_cast<double>(mrow) * static_cast<double>(rows);
   int ex = 0;
-  if (!(b <= 3.0e38f)) {
+  if (!(b <= 1.0e300)) {
     finite = false;
-  } else if (b > 0.0f) {
+  } else if (b > 0.0) {
     int e2 = 0;
-    frexpf(b, &e2);  // b < 2^e2
+    frexp(b, &e2);  // b < 2^e2
     ex = 29 - e2;
   }
   int lg = 0;  // ceil(log2(rows))
@@ -1377,8 +1378,9 @@ hipError_t run_grid_fixed(const pg_plan* p, const pg_kernels* k, const float2* v
   hipLaunchKernelGGL(table_bound_kernel<TapT>, dim3(static_cast<unsigned>(std::min<int64_t>((entries + 255) / 256, 8192))),
                      dim3(256), 0, s, k->table.as<TapT>(), entries, bound + 1);
   hipLaunchKernelGGL(fixed_exponent_kernel, dim3(1), dim3(1), 0, s, bound, static_cast<double>(p->n_kept), exp);
-  int nq = NP;
-  while (nq > 1 && 2 * (k->lds_bytes / NP * nq) + kSharedScratch > 163840) nq /= 2;
+  // one output plane per workgroup: the fastest shape of the shared-tap kernel on the full-pol
+  // workload, and one that fits wherever the kernel fits at all
+  const int nq = 1;
   const size_t sub = 2 * (k->lds_bytes / NP * nq);
   if (sub + kSharedScratch <= 163840) {
     auto launch = [&](auto fn) -> hipError_t {
@@ -1390,13 +1392,7 @@ hipError_t run_grid_fixed(const pg_plan* p, const pg_kernels* k, const float2* v
                          FixedSink{acc, exp});
       return hipSuccess;
     };
-    if constexpr (NP == 4) {
-      if (nq == 2) e = launch(grid_shared_fixed_kernel<NP, TapT, 2>);
-      else if (nq == 1) e = launch(grid_shared_fixed_kernel<NP, TapT, 1>);
-      else e = launch(grid_shared_fixed_kernel<NP, TapT, NP>);
-    } else {
-      e = launch(grid_shared_fixed_kernel<NP, TapT, NP>);
-    }
+    e = launch(grid_shared_fixed_kernel<NP, TapT, 1>);
   } else {
     auto fn = grid_fixed_kernel<NP, TapT>;
     const size_t bytes = k->lds_bytes + kBandScratch;
