@@ -190,7 +190,7 @@ int plan_impl(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_
   *out = nullptr;
   if (nvis < 0 || nvis > 0x7ffffff0LL) return fail(PG_EINVAL, "nvis must be in [0, 2^31 - 16]");
   if (nvis > 0 && !uvw) return fail(PG_EINVAL, "uvw must be non-NULL when nvis > 0");
-  if (max_chunk < 1) return fail(PG_EINVAL, "max_chunk must be >= 1");
+  if (max_chunk < 1 || max_chunk > (1 << 30)) return fail(PG_EINVAL, "max_chunk must be in [1, 2^30]");
   auto* p = new (std::nothrow) pg_plan();
   if (!p) return fail(PG_ENOMEM, "host allocation failed");
   std::unique_ptr<pg_plan> guard(p);

@@ -504,16 +504,28 @@ __global__ __launch_bounds__(NW * 64) void grid_banded_kernel(const Item* __rest
 //     sum_c |Re V_c| + |Im V_c| (a bound on every value of the sub-grid and on the sum of the
 //     magnitudes of its terms, independent of summation order) below 2^29; visibilities are
 //     multiplied by 2^e as they are read, so every term y comes out already scaled;
-//   * each term is split into h = round(y) and l = trunc((y - h) 2^f), f = min(20, 30 - log2 rows):
-//     coarse words sum to less than 2^30, fine words to less than 2^29, and the pair holds the sum
-//     of the float32 terms to 2^-(e + f), far below float32 rounding;
-//   * real and imaginary words are packed into one 64-bit integer, im 2^32 + re (re sign-extended),
-//     whose sums decode exactly while |sum re| < 2^31: one 64-bit LDS atomic per word pair.
+//   * each term is split into h = floor(y) and l = trunc(fract(y) 2^f), f = min(20, 30 - log2 rows):
+//     coarse words sum to less than 2^30 in magnitude, fine words lie in [0, 2^f) and sum to less
+//     than 2^30, and the pair holds every float32 term to about one fine unit 2^-(e + f), far below
+//     float32 rounding;
+//   * real and imaginary words are packed into one 64-bit integer, im 2^32 + re, whose sums decode
+//     exactly while |sum re| < 2^31: one 64-bit LDS atomic per word pair.  Coarse real words are
+//     sign-extended into the upper half; fine words are never negative, so their pair is the two
+//     32-bit registers side by side.
 // The sub-grid of an item is therefore the same bits whatever the order of its additions.
 constexpr int kSharedScratch = 64;  // bytes after the sub-grid words: the per-wave maxima
 
 __device__ __forceinline__ unsigned long long pack_pair(int re, int im) {
   return static_cast<unsigned long long>((static_cast<long long>(im) << 32) + static_cast<long long>(re));
+}
+__device__ __forceinline__ unsigned long long pack_fine(unsigned re, unsigned im) {
+  return (static_cast<unsigned long long>(im) << 32) | re;
+}
+// floor to int in one instruction (the compiler emits a floor and a truncating conversion)
+__device__ __forceinline__ int floor_to_int(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
 }
 __device__ __forceinline__ int2 unpack_pair(unsigned long long v) {
   const int re = static_cast<int>(static_cast<unsigned>(v));
@@ -541,14 +553,11 @@ __device__ __forceinline__ void grid_rows_shared(unsigned long long* lds, int fi
       v[r][c] = make_float2(ldexpf(a.x, ex), ldexpf(a.y, ex));
     }
   }
-  TapCursor cur(lane, ly0, lx0, inv_s, S, P);
-  uint32_t boff = static_cast<uint32_t>(lane) * TB;
-  for (int t = lane; t < SS; t += 64) {
-    float2 tap[NQ * NP];
-    tc.load_at(boff, tap);
-    const int off = cur.off;
-    boff += 64 * TB;
-    cur.advance(step);
+  // one tap of the footprint for all R rows; off = the tap's sub-grid word for the run's first row
+  auto tap_rows = [&](int off, const float2 (&tap)[NQ * NP]) {
+    // an opaque copy of the cursor: the compiler would otherwise keep one strength-reduced address
+    // per row and word, each stepped on every pass
+    asm volatile("" : "+v"(off));
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -560,13 +569,52 @@ __device__ __forceinline__ void grid_rows_shared(unsigned long long* lds, int fi
           yr = fmaf(a.x, v[r][c].x, fmaf(-a.y, v[r][c].y, yr));
           yi = fmaf(a.x, v[r][c].y, fmaf(a.y, v[r][c].x, yi));
         }
-        const float hr = rintf(yr), hi = rintf(yi);
         unsigned long long* cell = lds + q * WP + off + d[r];
-        atomicAdd(cell, pack_pair(static_cast<int>(hr), static_cast<int>(hi)));
-        // fine words truncated toward zero: the residual left is below one fine unit
-        atomicAdd(cell + fine_off, pack_pair(static_cast<int>((yr - hr) * fscale), static_cast<int>((yi - hi) * fscale)));
+        atomicAdd(cell, pack_pair(floor_to_int(yr), floor_to_int(yi)));
+        // fract(y) = y - floor(y) in [0, 1), truncated to f bits: the residual is below one fine unit
+        atomicAdd(cell + fine_off, pack_fine(static_cast<unsigned>(__builtin_amdgcn_fractf(yr) * fscale),
+                                             static_cast<unsigned>(__builtin_amdgcn_fractf(yi) * fscale)));
       }
     }
+  };
+  // Lane u takes taps u, u + 64, ... in passes of 64; after the full passes, a last pass takes the
+  // SS mod 64 taps left (if any) on the lanes that have one.  The taps of the next pass are loaded
+  // while this pass's rows are computed (two buffers, alternating; loads past the last tap read tap
+  // SS - 1 and are not used), in a loop without branches so that each wait covers only the buffer
+  // it needs.  When S divides 64 the footprint advances by whole rows and the cursor needs no wrap.
+  TapCursor cur(lane, ly0, lx0, inv_s, S, P);
+  const int full = SS >> 6;
+  const bool tail_lane = lane < SS - (full << 6);
+  const uint32_t b_last = static_cast<uint32_t>(SS - 1) * TB;
+  const uint32_t b0 = static_cast<uint32_t>(lane) * TB;
+  auto load_pass = [&](int p, float2 (&tap)[NQ * NP]) {
+    tc.load_at(min(b0 + static_cast<uint32_t>(p) * (64 * TB), b_last), tap);
+  };
+  auto run = [&](auto advance) {
+    float2 ta[NQ * NP], tb[NQ * NP];
+    load_pass(0, ta);
+    int p = 0;
+    for (; p + 2 <= full; p += 2) {
+      load_pass(p + 1, tb);
+      tap_rows(cur.off, ta);
+      advance();
+      load_pass(p + 2, ta);
+      tap_rows(cur.off, tb);
+      advance();
+    }
+    if (p < full) {  // one full pass left, in ta; the tail pass (if any) goes to tb
+      load_pass(p + 1, tb);
+      tap_rows(cur.off, ta);
+      advance();
+      if (tail_lane) tap_rows(cur.off, tb);
+    } else if (tail_lane) {  // ta holds the tail pass
+      tap_rows(cur.off, ta);
+    }
+  };
+  if (step.dt == 0) {
+    run([&]() { cur.off += step.doff; });
+  } else {
+    run([&]() { cur.advance(step); });
   }
 }
 

@@ -131,6 +131,10 @@ def test_empty_plan_and_all_dropped(case):
 
 def test_flag_checks_and_scratch_allocation_failure(case):
     w, vis, _, kg = case
+    # items are capped at 2^30 rows, the size the fixed-point bounds are derived for
+    for bad in (0, (1 << 30) + 1):
+        with pytest.raises(pg.PolgridError, match="max_chunk"):
+            pg.plan(kg, dev(w.uvw), max_chunk=bad)
     p = pg.plan(kg, dev(w.uvw), max_chunk=512)
     with pytest.raises(pg.PolgridError, match="PG_DETERMINISTIC"):
         pg.grid(p, kg, dev(vis), variant=pg.VARIANT_ATOMIC, deterministic=True)
