@@ -533,7 +533,8 @@ __device__ __forceinline__ int2 unpack_pair(unsigned long long v) {
   return make_int2(re, im);
 }
 
-template <int NP, typename TapT, int R, int NQ>
+// PF: two tap buffers (the next pass's taps in flight); off where the registers would not hold them
+template <int NP, typename TapT, int R, int NQ, bool PF>
 __device__ __forceinline__ void grid_rows_shared(unsigned long long* lds, int fine_off, const TapT* __restrict__ pt,
                                                  int j, int m_ly, int m_lx, int m_k, const float2* __restrict__ vis,
                                                  int S, int SS, int P, int WP, float inv_s, const FootStep& step,
@@ -591,24 +592,37 @@ __device__ __forceinline__ void grid_rows_shared(unsigned long long* lds, int fi
     tc.load_at(min(b0 + static_cast<uint32_t>(p) * (64 * TB), b_last), tap);
   };
   auto run = [&](auto advance) {
-    float2 ta[NQ * NP], tb[NQ * NP];
-    load_pass(0, ta);
-    int p = 0;
-    for (; p + 2 <= full; p += 2) {
-      load_pass(p + 1, tb);
-      tap_rows(cur.off, ta);
-      advance();
-      load_pass(p + 2, ta);
-      tap_rows(cur.off, tb);
-      advance();
-    }
-    if (p < full) {  // one full pass left, in ta; the tail pass (if any) goes to tb
-      load_pass(p + 1, tb);
-      tap_rows(cur.off, ta);
-      advance();
-      if (tail_lane) tap_rows(cur.off, tb);
-    } else if (tail_lane) {  // ta holds the tail pass
-      tap_rows(cur.off, ta);
+    if constexpr (PF) {
+      float2 ta[NQ * NP], tb[NQ * NP];
+      load_pass(0, ta);
+      int p = 0;
+      for (; p + 2 <= full; p += 2) {
+        load_pass(p + 1, tb);
+        tap_rows(cur.off, ta);
+        advance();
+        load_pass(p + 2, ta);
+        tap_rows(cur.off, tb);
+        advance();
+      }
+      if (p < full) {  // one full pass left, in ta; the tail pass (if any) goes to tb
+        load_pass(p + 1, tb);
+        tap_rows(cur.off, ta);
+        advance();
+        if (tail_lane) tap_rows(cur.off, tb);
+      } else if (tail_lane) {  // ta holds the tail pass
+        tap_rows(cur.off, ta);
+      }
+    } else {
+      float2 ta[NQ * NP];
+      for (int p = 0; p < full; ++p) {
+        load_pass(p, ta);
+        tap_rows(cur.off, ta);
+        advance();
+      }
+      if (tail_lane) {
+        load_pass(full, ta);
+        tap_rows(cur.off, ta);
+      }
     }
   };
   if (step.dt == 0) {
@@ -683,6 +697,7 @@ __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __re
   const int fbits = min(20, 30 - lg);
   const float fscale = ldexpf(1.0f, fbits);
   const FootStep step(S, P);
+  constexpr bool kPF = NW * NQ <= 16;  // room for two tap buffers in the registers
   const int per = (rows + NW - 1) / NW;
   const int w0 = it.start + wave * per, w1 = min(it.end, w0 + per);
   for (int blk = w0; blk < w1 && finite; blk += 64) {
@@ -704,19 +719,19 @@ __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __re
       run = __builtin_amdgcn_readfirstlane(run);
       const TapT* pt = table + pl.offset + (static_cast<size_t>(ph) * NP * NP + q0 * NP) * SS;
       if (run == 8) {
-        grid_rows_shared<NP, TapT, 8, NQ>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
-                                          ex, fscale);
+        grid_rows_shared<NP, TapT, 8, NQ, kPF>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
+                                               ex, fscale);
       } else if (run >= 4) {
-        grid_rows_shared<NP, TapT, 4, NQ>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
-                                          ex, fscale);
+        grid_rows_shared<NP, TapT, 4, NQ, kPF>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
+                                               ex, fscale);
         run = 4;
       } else if (run >= 2) {
-        grid_rows_shared<NP, TapT, 2, NQ>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
-                                          ex, fscale);
+        grid_rows_shared<NP, TapT, 2, NQ, kPF>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
+                                               ex, fscale);
         run = 2;
       } else {
-        grid_rows_shared<NP, TapT, 1, NQ>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
-                                          ex, fscale);
+        grid_rows_shared<NP, TapT, 1, NQ, kPF>(lds, fine_off, pt, j, m_ly, m_lx, m_k, vis, S, SS, P, WP, inv_s, step, lane,
+                                               ex, fscale);
       }
       j += run;
     }

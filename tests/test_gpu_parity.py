@@ -431,10 +431,10 @@ def test_large_support_float16_tables(big_case):
     assert rel(got, gridding.grid(w.geom, kernels.round_tables(tg, np.float16), w.uvw, vis)) < TOL
 
 
-@pytest.mark.parametrize("planes,waves,group", [(0, 4, 1), (1, 4, 2), (2, 8, 1), (0, 16, 64), (1, 6, 5)])
+@pytest.mark.parametrize("planes,waves,group", [(0, 4, 1), (1, 4, 2), (2, 8, 1), (0, 16, 64), (2, 16, 1), (1, 6, 5)])
 def test_c2_shared_tap_gridder(c2_case, planes, waves, group):
     """The shared-tap gridder (fixed-point LDS accumulation) at every waves-per-workgroup setting,
-    output-plane split and XCD grouping; float16 tables too."""
+    output-plane split and XCD grouping (with one and with two tap buffers); float16 tables too."""
     w, vis, tg, _, kg, _ = c2_case
     p = pg.plan(kg, dev(w.uvw), max_chunk=100).set_launch(3, waves, waves, group, planes)
     got = host(pg.grid(p, kg, dev(vis)))
