@@ -635,7 +635,9 @@ __device__ __forceinline__ void grid_rows_shared(unsigned long long* lds, int fi
 // FIXED: the reproducible mode's flush.  The item's values are exact integers at the scale
 // 2^(e + f); they are moved to the launch-wide scale of the 64-bit accumulators by a shift (exact
 // when it is a left shift, a floor when right) and added with integer atomics.
-template <int NP, typename TapT, int NW, int NQ = NP, bool FIXED = false>
+// TWO_BUFFERS: the single-plan launches take two tap buffers where the registers hold them; the
+// batched launch keeps one (measured faster there)
+template <int NP, typename TapT, int NW, int NQ = NP, bool FIXED = false, bool TWO_BUFFERS = true>
 __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __restrict__ fine,
                                                  const int32_t* __restrict__ perm, const float2* __restrict__ vis,
                                                  const TapT* __restrict__ table, const PlaneInfo* __restrict__ planes,
@@ -697,7 +699,7 @@ __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __re
   const int fbits = min(20, 30 - lg);
   const float fscale = ldexpf(1.0f, fbits);
   const FootStep step(S, P);
-  constexpr bool kPF = NW * NQ <= 16;  // room for two tap buffers in the registers
+  constexpr bool kPF = TWO_BUFFERS && NW * NQ <= 16;  // and room for them in the registers
   const int per = (rows + NW - 1) / NW;
   const int w0 = it.start + wave * per, w1 = min(it.end, w0 + per);
   for (int blk = w0; blk < w1 && finite; blk += 64) {
@@ -959,8 +961,9 @@ __global__ __launch_bounds__(NW * 64) void grid_shared_batch(const FieldArgs* __
   if (wr.x < 0) return;
   const int part = blockIdx.x % (NP / NQ);
   ConstFieldArgs& fa = ((ConstFieldArgs*)fields)[wr.x];
-  grid_item_shared<NP, TapT, NW, NQ>(fa.items[wr.y], fa.fine, fa.perm, fa.vis, static_cast<const TapT*>(fa.table),
-                                     fa.planes, fa.kbound, fa.os, fa.n, fa.grid, flags, sub_bytes, lds_f, part * NQ);
+  grid_item_shared<NP, TapT, NW, NQ, false, false>(fa.items[wr.y], fa.fine, fa.perm, fa.vis,
+                                                   static_cast<const TapT*>(fa.table), fa.planes, fa.kbound, fa.os,
+                                                   fa.n, fa.grid, flags, sub_bytes, lds_f, part * NQ);
 }
 
 // R consecutive rows of a work item that share one kernel phase (rows are phase-sorted inside a
