@@ -655,15 +655,29 @@ __device__ __forceinline__ void grid_item_shared(const Item it, const int2* __re
   // largest row sum of |Re V_c| + |Im V_c| over the item (a maximum: the same in every thread and
   // for any partition of the rows)
   float m1 = 0.0f;
-  for (int i = it.start + static_cast<int>(threadIdx.x); i < it.end; i += NW * 64) {
-    const size_t k = static_cast<size_t>(perm[i]);
-    float a1 = 0.0f;
+  constexpr int kRowsPerPass = 2;  // rows per thread whose loads are in flight together
+  for (int i0 = it.start + static_cast<int>(threadIdx.x); i0 < it.end; i0 += kRowsPerPass * NW * 64) {
+    int k[kRowsPerPass];
 #pragma unroll
-    for (int c = 0; c < NP; ++c) {
-      const float2 a = vis[k * NP + c];
-      a1 += fabsf(a.x) + fabsf(a.y);
+    for (int u = 0; u < kRowsPerPass; ++u) {
+      const int i = i0 + u * NW * 64;
+      k[u] = i < it.end ? perm[i] : -1;
     }
-    m1 = (a1 > m1 || a1 != a1) ? a1 : m1;  // a NaN row wins, so a non-finite item is recognised
+    float2 a[kRowsPerPass][NP];
+#pragma unroll
+    for (int u = 0; u < kRowsPerPass; ++u) {
+      const size_t kk = static_cast<size_t>(k[u] < 0 ? 0 : k[u]);  // row 0 stands in, unused
+#pragma unroll
+      for (int c = 0; c < NP; ++c) a[u][c] = vis[kk * NP + c];
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsPerPass; ++u) {
+      if (k[u] < 0) continue;
+      float a1 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) a1 += fabsf(a[u][c].x) + fabsf(a[u][c].y);
+      m1 = (a1 > m1 || a1 != a1) ? a1 : m1;  // a NaN row wins, so a non-finite item is recognised
+    }
   }
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
@@ -1045,15 +1059,32 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
   const float inv_s = 1.0f / static_cast<float>(S);
   const bool shift = (flags & PG_FFTSHIFT) != 0;
   const size_t pstride = static_cast<size_t>(n) * n;
-  for (int idx = threadIdx.x; idx < W * W; idx += (NW * 64)) {
-    const int y = idx / W, x = idx - y * W;
-    const int X = it.ox + x, Y = it.oy + y;
-    const bool in = X < n && Y < n;
-    const float sg = (shift && ((X + Y) & 1)) ? -1.0f : 1.0f;
+  // sub-grid fill: kFill cells per thread per pass, all their loads issued before the first LDS
+  // write, so that a pass costs one memory round trip (one workgroup per CU leaves nothing else to
+  // run meanwhile)
+  constexpr int kFill = 4;
+  const int cells = W * W;
+  for (int base = threadIdx.x; base < cells; base += kFill * NW * 64) {
+    float2 g[kFill][NP];
+    int dst[kFill];
+    float sg[kFill];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const float2 g = in ? grid[q * pstride + static_cast<size_t>(Y) * n + X] : make_float2(0.0f, 0.0f);
-      lds[q * WP + y * P + x] = make_float2(sg * g.x, sg * g.y);
+    for (int u = 0; u < kFill; ++u) {
+      const int idx = base + u * NW * 64;
+      const int y = idx / W, x = idx - y * W;
+      const int X = it.ox + x, Y = it.oy + y;
+      const bool in = idx < cells && X < n && Y < n;
+      dst[u] = idx < cells ? y * P + x : -1;
+      sg[u] = (shift && ((X + Y) & 1)) ? -1.0f : 1.0f;
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        g[u][q] = in ? grid[q * pstride + static_cast<size_t>(Y) * n + X] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      if (dst[u] < 0) continue;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) lds[q * WP + dst[u]] = make_float2(sg[u] * g[u][q].x, sg[u] * g[u][q].y);
     }
   }
   __syncthreads();
