@@ -980,6 +980,46 @@ __global__ __launch_bounds__(NW * 64) void grid_shared_batch(const FieldArgs* __
                                                    fa.n, fa.grid, flags, sub_bytes, lds_f, part * NQ);
 }
 
+// Sums over the 64 lanes of the 2 NC R accumulators of a degrid pass (row r, value e = 2 c + re/im
+// at flat index v = 2 NC r + e), NC >= 2, by halving: a 32-lane swap pairs values v and v + 1 (lanes
+// 0-31 then carry v, lanes 32-63 v + 1, each summed over the two halves), a 16-lane swap pairs those
+// registers (rows 0-3 of register h then carry v = 4 h, 4 h + 2, 4 h + 1, 4 h + 3), and four DPP adds
+// finish each 16-lane row.  About 2.5 instructions per value instead of ten for a separate reduction
+// of each, and the first lane of each row stores its value (one store per register).
+template <int NP, int NC, int R>
+__device__ __forceinline__ void degrid_sum_rows(float (&acc)[R][2 * NC], int j, int m_k,
+                                                float2* __restrict__ vis_out, int flags, int lane, int c0) {
+  constexpr int E = 2 * NC, M = R * E;  // E is a multiple of 4
+  float half[M / 2];
+#pragma unroll
+  for (int i = 0; i < M / 2; ++i) {
+    const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[(2 * i) / E][(2 * i) % E]),
+                                                     __float_as_uint(acc[(2 * i + 1) / E][(2 * i + 1) % E]),
+                                                     false, false);
+    half[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+  }
+  const int rho = lane >> 4;
+  const int e_row = (rho & 1) * 2 + (rho >> 1);  // value offset carried by 16-lane row rho
+  float* out = reinterpret_cast<float*>(vis_out);
+#pragma unroll
+  for (int h = 0; h < M / 4; ++h) {
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(half[2 * h]), __float_as_uint(half[2 * h + 1]),
+                                                     false, false);
+    float v = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    v += dpp_move<0x128>(v);  // row_ror 8
+    v += dpp_move<0x124>(v);  // row_ror 4
+    v += dpp_move<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0xb1>(v);   // quad_perm [1, 0, 3, 2]: every lane of the row holds its sum
+    const int r = (4 * h) / E;               // the same row for the four values of register h
+    const int e = (4 * h) % E + e_row;
+    const int k = __builtin_amdgcn_readlane(m_k, j + r);
+    if ((lane & 15) == 0) {
+      float* o = out + (static_cast<size_t>(k) * NP + c0 + (e >> 1)) * 2 + (e & 1);
+      *o = (flags & PG_ACCUMULATE) ? *o + v : v;
+    }
+  }
+}
+
 // R consecutive rows of a work item that share one kernel phase (rows are phase-sorted inside a
 // tile), degridded together: every tap is loaded once and applied to all R rows, whose sub-grid
 // positions differ by a wave-uniform offset.  One 64-lane sum per row and output value; lane 63
@@ -1029,20 +1069,24 @@ __device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase
       }
     }
   }
+  if constexpr (NC >= 2) {
+    degrid_sum_rows<NP, NC, R>(acc, j, m_k, vis_out, flags, lane, c0);
+  } else {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < R; ++r) {
 #pragma unroll
-    for (int c = 0; c < 2 * NC; ++c) acc[r][c] = wave_sum_to_lane63(acc[r][c]);
-    const int k = __builtin_amdgcn_readlane(m_k, j + r);
-    if (lane == 63) {
+      for (int c = 0; c < 2 * NC; ++c) acc[r][c] = wave_sum_to_lane63(acc[r][c]);
+      const int k = __builtin_amdgcn_readlane(m_k, j + r);
+      if (lane == 63) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (flags & PG_ACCUMULATE) {
-          float2& o = vis_out[static_cast<size_t>(k) * NP + c0 + c];
-          o = make_float2(o.x + acc[r][2 * c], o.y + acc[r][2 * c + 1]);
-        } else {
-          vis_out[static_cast<size_t>(k) * NP + c0 + c] = make_float2(acc[r][2 * c], acc[r][2 * c + 1]);
-        }
+        for (int c = 0; c < NC; ++c)
+          if (flags & PG_ACCUMULATE) {
+            float2& o = vis_out[static_cast<size_t>(k) * NP + c0 + c];
+            o = make_float2(o.x + acc[r][2 * c], o.y + acc[r][2 * c + 1]);
+          } else {
+            vis_out[static_cast<size_t>(k) * NP + c0 + c] = make_float2(acc[r][2 * c], acc[r][2 * c + 1]);
+          }
+      }
     }
   }
 }
