@@ -980,6 +980,18 @@ __global__ __launch_bounds__(NW * 64) void grid_shared_batch(const FieldArgs* __
                                                    fa.n, fa.grid, flags, sub_bytes, lds_f, part * NQ);
 }
 
+// Degrid sub-grid layout in LDS: full-pol planes in pairs, [q / 2][W][P][q % 2], so that a row
+// reads planes (0, 1) and (2, 3) as two 16-byte values from consecutive cells (16-byte stride:
+// no bank conflicts along a footprint row); one plane: [W][P].
+template <int NP>
+__device__ __forceinline__ int degrid_lds_index(int q, int cell, int WP) {
+  if constexpr (NP == 1) {
+    return cell;
+  } else {
+    return ((q >> 1) * WP + cell) * 2 + (q & 1);
+  }
+}
+
 // Sums over the 64 lanes of the 2 NC R accumulators of a degrid pass (row r, value e = 2 c + re/im
 // at flat index v = 2 NC r + e), NC >= 2, by halving: a 32-lane swap pairs values v and v + 1 (lanes
 // 0-31 then carry v, lanes 32-63 v + 1, each summed over the two halves), a 16-lane swap pairs those
@@ -1035,6 +1047,7 @@ __device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase
   // which sit in every (NP / NC)-th 16-byte chunk of the phase block
   const TapChunks<NP * NC, TapT> tc = NC == NP ? TapChunks<NP * NC, TapT>(phase_table, SS)
                                                : TapChunks<NP * NC, TapT>(phase_table, SS, c0 / NC, NP / NC);
+  const float2* lds_hi = lds + 2 * WP;  // planes (2, 3) of the plane-pair layout
   const int ly0 = __builtin_amdgcn_readlane(m_ly, j), lx0 = __builtin_amdgcn_readlane(m_lx, j);
   int d[R];
 #pragma unroll
@@ -1059,7 +1072,7 @@ __device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase
     for (int r = 0; r < R; ++r) {
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        const float2 g = lds[q * WP + off + d[r]];
+        const float2 g = NP == 1 ? lds[off + d[r]] : (q < 2 ? lds : lds_hi)[2 * (off + d[r]) + (q & 1)];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const float2 a = tap[q * NC + c];  // conj(a) * g
@@ -1097,7 +1110,7 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
                                             const PlaneInfo* __restrict__ planes, int os, int n,
                                             const float2* __restrict__ grid, float2* __restrict__ vis_out,
                                             int flags, float* lds_f, int c0 = 0) {
-  float2* lds = reinterpret_cast<float2*>(lds_f);  // [q][W][P]
+  float2* lds = reinterpret_cast<float2*>(lds_f);  // plane pairs: [q / 2][W][P][q % 2]
   const PlaneInfo pl = planes[it.plane];
   const int S = pl.support, W = pl.width, P = pl.pitch, WP = W * P, SS = S * S, half = S * os / 2;
   const float inv_s = 1.0f / static_cast<float>(S);
@@ -1128,7 +1141,8 @@ __device__ __forceinline__ void degrid_item(const Item it, const int2* __restric
     for (int u = 0; u < kFill; ++u) {
       if (dst[u] < 0) continue;
 #pragma unroll
-      for (int q = 0; q < NP; ++q) lds[q * WP + dst[u]] = make_float2(sg[u] * g[u][q].x, sg[u] * g[u][q].y);
+      for (int q = 0; q < NP; ++q)
+        lds[degrid_lds_index<NP>(q, dst[u], WP)] = make_float2(sg[u] * g[u][q].x, sg[u] * g[u][q].y);
     }
   }
   __syncthreads();
