@@ -992,6 +992,23 @@ __device__ __forceinline__ int degrid_lds_index(int q, int cell, int WP) {
   }
 }
 
+// The NP grid values of one sub-grid cell: one plane, or the two plane pairs as aligned 16-byte
+// reads (ds_read_b128; two 8-byte halves would each meet a two-way bank conflict at this stride)
+template <int NP>
+__device__ __forceinline__ void degrid_cell(const float2* lds, const float2* lds_hi, int cell, float2 (&g)[NP]) {
+  if constexpr (NP == 1) {
+    g[0] = lds[cell];
+  } else {
+    static_assert(NP == 4, "full-pol sub-grids hold two plane pairs");
+    const float4 a = reinterpret_cast<const float4*>(lds)[cell];
+    const float4 b = reinterpret_cast<const float4*>(lds_hi)[cell];
+    g[0] = make_float2(a.x, a.y);
+    g[1] = make_float2(a.z, a.w);
+    g[2] = make_float2(b.x, b.y);
+    g[3] = make_float2(b.z, b.w);
+  }
+}
+
 // Sums over the 64 lanes of the 2 NC R accumulators of a degrid pass (row r, value e = 2 c + re/im
 // at flat index v = 2 NC r + e), NC >= 2, by halving: a 32-lane swap pairs values v and v + 1 (lanes
 // 0-31 then carry v, lanes 32-63 v + 1, each summed over the two halves), a 16-lane swap pairs those
@@ -1070,9 +1087,11 @@ __device__ __forceinline__ void degrid_rows(const float2* lds, const TapT* phase
     cur.advance(step);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      float2 gq[NP];
+      degrid_cell<NP>(lds, lds_hi, off + d[r], gq);
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        const float2 g = NP == 1 ? lds[off + d[r]] : (q < 2 ? lds : lds_hi)[2 * (off + d[r]) + (q & 1)];
+        const float2 g = gq[q];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const float2 a = tap[q * NC + c];  // conj(a) * g
