@@ -187,7 +187,8 @@ void pg_kernels_destroy(pg_kernels* k);
  * oversampling phase; stable sort by (plane, tile_y, tile_x, phase_y, phase_x);
  * work items are runs of one (plane, tile) cut into chunks of at most max_chunk, in [1, 2^30]
  * (the fixed-point bounds of the shared-tap gridder hold for items of up to 2^30 rows).
- * Synchronises `stream` once and returns the drop count in *n_dropped (host, may be NULL).
+ * Synchronises `stream` (to size the outputs, and once more before returning, so the plan is
+ * complete for any stream) and returns the drop count in *n_dropped (host, may be NULL).
  * nvis may be 0.  Errors: PG_EINVAL, PG_ENOMEM, PG_EHIP. */
 int pg_plan_create(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_chunk,
                    void* stream, pg_plan** out, int64_t* n_dropped);

@@ -212,24 +212,37 @@ int plan_impl(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_
     *out = guard.release();
     return PG_OK;
   }
-  DevBuf keys, keys_t, vals, vals_t, fine_all, scratch, counts;
+  // the binning temporaries share one allocation (each allocation may call back into a caller's
+  // allocator): keys and sort buffers, fine positions, scratch and counts, 256-byte aligned parts
   const int64_t sc = std::max(radix_scratch_elems(nvis), plan_scratch_elems(nvis));
-  if (!keys.alloc(8 * nvis, s) || !keys_t.alloc(8 * nvis, s) || !vals.alloc(4 * nvis, s) ||
-      !vals_t.alloc(4 * nvis, s) || !fine_all.alloc(8 * nvis, s) || !scratch.alloc(4 * sc, s) ||
-      !counts.alloc(16, s) || !p->perm.alloc(4 * nvis, s))
-    return fail(PG_ENOMEM, "device allocation failed in plan");
-  PG_HIP(launch_fill_zero(counts.p, 16, s), "zero counts");
+  const size_t part_bytes[7] = {static_cast<size_t>(8 * nvis), static_cast<size_t>(8 * nvis),
+                                static_cast<size_t>(4 * nvis), static_cast<size_t>(4 * nvis),
+                                static_cast<size_t>(8 * nvis), static_cast<size_t>(4 * sc), 16};
+  size_t part_off[7], tmp_bytes = 0;
+  for (int i = 0; i < 7; ++i) {
+    part_off[i] = tmp_bytes;
+    tmp_bytes += (part_bytes[i] + 255) / 256 * 256;
+  }
+  DevBuf tmp;
+  if (!tmp.alloc(tmp_bytes, s) || !p->perm.alloc(4 * nvis, s)) return fail(PG_ENOMEM, "device allocation failed in plan");
+  char* base = static_cast<char*>(tmp.p);
+  auto* keys = reinterpret_cast<uint64_t*>(base + part_off[0]);
+  auto* keys_t = reinterpret_cast<uint64_t*>(base + part_off[1]);
+  auto* vals = reinterpret_cast<int32_t*>(base + part_off[2]);
+  auto* vals_t = reinterpret_cast<int32_t*>(base + part_off[3]);
+  auto* fine_all = reinterpret_cast<int2*>(base + part_off[4]);
+  auto* scratch = reinterpret_cast<int32_t*>(base + part_off[5]);
+  auto* counts = reinterpret_cast<int32_t*>(base + part_off[6]);
+  PG_HIP(launch_fill_zero(counts, 16, s), "zero counts");
   PG_HIP(launch_plan_keys(uvw, nvis, k->n, k->cell, k->os, k->nplanes, k->w_dev.as<double>(), k->planes.as<PlaneInfo>(),
-                          nt, drop_key, keys.as<uint64_t>(), vals.as<int32_t>(), fine_all.as<int2>(), s), "plan keys");
+                          nt, drop_key, keys, vals, fine_all, s), "plan keys");
   bool in_tmp = false;
-  PG_HIP(radix_sort_pairs(keys.as<uint64_t>(), vals.as<int32_t>(), keys_t.as<uint64_t>(), vals_t.as<int32_t>(), nvis,
-                          bits, scratch.as<int32_t>(), sc, s, &in_tmp), "radix sort");
-  const uint64_t* ks = in_tmp ? keys_t.as<uint64_t>() : keys.as<uint64_t>();
-  const int32_t* vs = in_tmp ? vals_t.as<int32_t>() : vals.as<int32_t>();
-  PG_HIP(launch_plan_stage_a(ks, nvis, drop_key, k->os, max_chunk, counts.as<int32_t>(), scratch.as<int32_t>(), sc, s),
-         "plan items");
+  PG_HIP(radix_sort_pairs(keys, vals, keys_t, vals_t, nvis, bits, scratch, sc, s, &in_tmp), "radix sort");
+  const uint64_t* ks = in_tmp ? keys_t : keys;
+  const int32_t* vs = in_tmp ? vals_t : vals;
+  PG_HIP(launch_plan_stage_a(ks, nvis, drop_key, k->os, max_chunk, counts, scratch, sc, s), "plan items");
   int32_t hc[4] = {0, 0, 0, 0};
-  PG_HIP(hipMemcpyAsync(hc, counts.p, 16, hipMemcpyDeviceToHost, s), "read counts");
+  PG_HIP(hipMemcpyAsync(hc, counts, 16, hipMemcpyDeviceToHost, s), "read counts");
   PG_HIP(hipStreamSynchronize(s), "plan sync");
   p->n_kept = hc[0];
   p->n_items = hc[1];
@@ -238,8 +251,8 @@ int plan_impl(const pg_kernels* k, const double* uvw, int64_t nvis, int32_t max_
   if (!p->fine.alloc(8 * std::max<int64_t>(p->n_kept, 1), s) || !p->items.alloc(sizeof(Item) * std::max<int64_t>(p->n_items, 1), s))
     return fail(PG_ENOMEM, "device allocation failed in plan");
   PG_HIP(hipMemcpyAsync(p->perm.p, vs, 4 * nvis, hipMemcpyDeviceToDevice, s), "copy perm");
-  PG_HIP(launch_plan_scatter(ks, vs, fine_all.as<int2>(), p->n_kept, n_runs, nvis, k->os, nt, max_chunk,
-                             k->planes.as<PlaneInfo>(), scratch.as<int32_t>(), p->fine.as<int2>(), p->items.as<Item>(), s),
+  PG_HIP(launch_plan_scatter(ks, vs, fine_all, p->n_kept, n_runs, nvis, k->os, nt, max_chunk,
+                             k->planes.as<PlaneInfo>(), scratch, p->fine.as<int2>(), p->items.as<Item>(), s),
          "plan scatter");
   PG_HIP(hipStreamSynchronize(s), "plan sync");
   if (n_dropped) *n_dropped = p->n_dropped;
