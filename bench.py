@@ -307,7 +307,8 @@ def bench_batched(steps, warmup):
         launch = autotune.apply(w.geom, 4, pg.STORE_F16)
         g = launch.geom
         jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
-        kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=0.2, storage=pg.STORE_F16)
+        kg = pg.make_kernels(autotune.batch_grid_geom(launch), 4, pg.KIND_GRID, jones=jones, eps_null=0.2,
+                             storage=pg.STORE_F16)
         kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones, storage=pg.STORE_F16)
         uvw = torch.from_numpy(w.uvw).cuda()
         ks.append((kg, kd))

@@ -22,7 +22,10 @@ from collections import namedtuple
 import numpy as np
 
 Launch = namedtuple("Launch", "geom max_chunk variant grid_waves degrid_waves xcd_group batch_grid_waves "
-                               "batch_degrid_waves grid_planes degrid_corrs")
+                               "batch_degrid_waves grid_planes degrid_corrs batch_grid")
+# the batched gridder's own shape where it differs from the single-plan one: geometry (tiles),
+# chunk length, variant and output planes per workgroup; the batched degrid keeps the entry's
+BatchGrid = namedtuple("BatchGrid", "geom max_chunk variant planes")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
@@ -91,25 +94,40 @@ def apply(geom, npol, storage) -> Launch:
     cfg = tuned_config(npol, storage, geom.os, geom.support)
     g = copy.copy(geom)
     if cfg is None:
-        return Launch(g, 1024, 0, 16, 16, 1, 16, 16, 0, 0)
+        return Launch(g, 1024, 0, 16, 16, 1, 16, 16, 0, 0, None)
     g.tile = np.asarray(cfg["grid"]["tiles"], dtype=np.int32)
     same = cfg["grid"]["wgs_per_cu"] == cfg["degrid"]["wgs_per_cu"]
     gw, dw = int(cfg["grid"]["waves"]), int(cfg["degrid"]["waves"]) if same else 16
     batch = cfg.get("batch", {})
+    bgrid = None
+    if "grid_wgs_per_cu" in batch:
+        tiles = tiles_for(geom.support, npol, int(batch["grid_wgs_per_cu"]))
+        if tiles is not None:
+            gb = copy.copy(geom)
+            gb.tile = tiles
+            bgrid = BatchGrid(gb, int(batch["grid_max_chunk"]), int(batch["grid_variant"]), int(batch["grid_planes"]))
     return Launch(g, int(cfg["grid"]["max_chunk"]), int(cfg["grid"].get("variant", 2)), gw, dw,
                   int(cfg.get("xcd_group", 1)), int(batch.get("grid_waves", gw)), int(batch.get("degrid_waves", dw)),
-                  int(cfg["grid"].get("planes", 0)), int(cfg["degrid"].get("corrs", 0)))
+                  int(cfg["grid"].get("planes", 0)), int(cfg["degrid"].get("corrs", 0)), bgrid)
+
+
+def batch_grid_geom(launch: Launch):
+    """Geometry (tiles) for the gridding kernels of a batched launch."""
+    return launch.batch_grid.geom if launch.batch_grid is not None else launch.geom
 
 
 def batch_plans(kernels_grid, kernels_degrid, uvw, launch: Launch):
     """(grid plan, degrid plan) for one field of a batched launch, with the batched kernels'
-    waves per workgroup (a batch takes its launch shape from its first field's plan)."""
+    waves per workgroup and, where the tuned entry gives one, the batched gridder's own chunk
+    length, variant and output planes (kernels_grid built on `batch_grid_geom(launch)`); a batch
+    takes its launch shape from its first field's plan."""
     from . import polgrid as pg
 
-    pg_ = pg.plan(kernels_grid, uvw, max_chunk=launch.max_chunk)
+    bgr = launch.batch_grid
+    pg_ = pg.plan(kernels_grid, uvw, max_chunk=bgr.max_chunk if bgr is not None else launch.max_chunk)
     pd_ = pg.plan(kernels_degrid, uvw, max_chunk=launch.max_chunk)
-    pg_.set_launch(launch.variant, launch.batch_grid_waves, launch.degrid_waves, launch.xcd_group, launch.grid_planes,
-                   launch.degrid_corrs)
+    pg_.set_launch(bgr.variant if bgr is not None else launch.variant, launch.batch_grid_waves, launch.degrid_waves,
+                   launch.xcd_group, bgr.planes if bgr is not None else launch.grid_planes, launch.degrid_corrs)
     pd_.set_launch(0, launch.grid_waves, launch.batch_degrid_waves, launch.xcd_group, launch.grid_planes,
                    launch.degrid_corrs)
     return pg_, pd_

@@ -188,7 +188,9 @@ def test_full_size_batched_fields_sampled():
         g = launch.geom
         w.geom = g
         jones = synth.jones_on_lattice(w.beam, g.mk, g.fov)
-        kg = pg.make_kernels(g, 4, pg.KIND_GRID, jones=jones, eps_null=0.2, storage=pg.STORE_F16)
+        # the batched gridder's own tiles (the tables do not depend on them)
+        kg = pg.make_kernels(autotune.batch_grid_geom(launch), 4, pg.KIND_GRID, jones=jones, eps_null=0.2,
+                             storage=pg.STORE_F16)
         kd = pg.make_kernels(g, 4, pg.KIND_DEGRID, jones=jones, storage=pg.STORE_F16)
         uvw = torch.from_numpy(w.uvw).cuda()
         pgr, pdg = autotune.batch_plans(kg, kd, uvw, launch)
