@@ -891,17 +891,11 @@ __global__ void vis_bound_kernel(const int32_t* __restrict__ perm, int64_t n_kep
   wave_max_to(out, m);
 }
 
-__device__ inline float2 tap_value(float2 t) { return t; }
-__device__ inline float2 tap_value(__half2 t) { return __half22float2(t); }
-
-template <typename TapT>
-__global__ void table_bound_kernel(const TapT* __restrict__ table, int64_t count, unsigned* __restrict__ out) {
+// Largest |Re| + |Im| of any table entry: the maximum of the per-plane, per-row bounds kept with the
+// tables (refreshed whenever a table is generated or written), without reading the table again.
+__global__ void kbound_max_kernel(const float* __restrict__ kbound, int n, unsigned* __restrict__ out) {
   float m = 0.0f;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const float2 t = tap_value(table[i]);
-    m = fmaxf(m, fabsf(t.x) + fabsf(t.y));
-  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, kbound[i]);
   wave_max_to(out, m);
 }
 
@@ -1548,9 +1542,7 @@ hipError_t run_grid_fixed(const pg_plan* p, const pg_kernels* k, const float2* v
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(vis_bound_kernel, dim3(static_cast<unsigned>(std::min<int64_t>((p->n_kept + 255) / 256, 4096))),
                      dim3(256), 0, s, p->perm.as<int32_t>(), p->n_kept, NP, vis, bound);
-  const int64_t entries = k->plane_offset.back();
-  hipLaunchKernelGGL(table_bound_kernel<TapT>, dim3(static_cast<unsigned>(std::min<int64_t>((entries + 255) / 256, 8192))),
-                     dim3(256), 0, s, k->table.as<TapT>(), entries, bound + 1);
+  hipLaunchKernelGGL(kbound_max_kernel, dim3(1), dim3(64), 0, s, k->kbound.as<float>(), 4 * k->nplanes, bound + 1);
   hipLaunchKernelGGL(fixed_exponent_kernel, dim3(1), dim3(1), 0, s, bound, static_cast<double>(p->n_kept), exp);
   // one output plane per workgroup: the fastest shape of the shared-tap kernel on the full-pol
   // workload, and one that fits wherever the kernel fits at all
