@@ -54,6 +54,21 @@ def test_apply_without_cache_entry_gives_defaults():
     assert np.array_equal(launch.geom.tile, g.tile)
 
 
+def test_batched_gridder_shape_only_where_the_entry_names_one():
+    """The float16 entry gives the batched gridder its own tiles and shape (one-workgroup-per-CU
+    tiles, shared taps, one plane, 1024-row items) while its degrid keeps the entry's tiles; the
+    float32 entry names none, so its batches use the single-plan shape."""
+    w = synth.config3()[0]
+    l16 = autotune.apply(w.geom, 4, 1)
+    bg = l16.batch_grid
+    assert bg is not None and (bg.variant, bg.planes, bg.max_chunk) == (3, 1, 1024)
+    assert np.array_equal(bg.geom.tile, autotune.tiles_for(w.geom.support, 4, 1))
+    assert autotune.batch_grid_geom(l16) is bg.geom
+    assert not np.array_equal(bg.geom.tile, l16.geom.tile)  # the degrid's tiles differ
+    l32 = autotune.apply(synth.config2().geom, 4, 0)
+    assert l32.batch_grid is None and autotune.batch_grid_geom(l32) is l32.geom
+
+
 def test_tuning_cache_is_well_formed():
     data = json.load(open(autotune.CACHE))
     for key, v in data.items():
